@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of the FRW two-field lattice leapfrog on one MI355X.
+
+Workload (default): the chaotic-inflation model of Sainio, arXiv:0911.5692,
+Sec. III — V = m^2 phi^2/2 + g^2 phi^2 chi^2/2 in program units (m = 1,
+G = g^2 phi0^2/m^2 = 2.5e5, r = 3/2, s = 0) on a 512^3 periodic lattice, FP32
+lattice arrays, vacuum-spectrum initial fluctuations from a fixed seed.
+
+A step is one leapfrog step of the whole path: the FP64 scale-factor update,
+the fused kick-drift sweep of both fields and the volume averages for the
+next a''.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gsite-updates/s per leapfrog step, 512³ 2-field FP32; % of HBM roofline"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lf_sweep.hip", "lf_internal.h"):
+        with open(os.path.join(ROOT, "paper_0911_5692_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different sweep source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("sweep_source_hash") != sweep_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, ic) -> dict:
+    import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    m = O.Model(**w.model())
+    st = O.start_physical(m, ic["f1"], ic["f2"], ic["u1"], ic["u2"], ic["a0"])
+    t0 = time.perf_counter()
+    O.evolve(st, 1)
+    per = time.perf_counter() - t0
+    n = max(1, min(12, int(15.0 / max(per, 1e-3))))
+    log(f"cpu baseline: 1 step {per:.2f} s, timing {n} more")
+    t0 = time.perf_counter()
+    O.evolve(st, n)
+    el = time.perf_counter() - t0
+    return {"value": w.sites * n / el / 1e9, "unit": "Gsite-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="m2phi2_512c_f32")
+    ap.add_argument("--kernel-steps", type=int, default=50,
+                    help="eager steps timed per kernel with HIP events (roofline)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU z-slab path is a design "
+              "(see DESIGN.md), not an implementation. Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_0911_5692_amd import Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    dtype = torch.float32 if w.dtype == "f32" else torch.float64
+    esize = 4 if w.dtype == "f32" else 8
+    log(f"workload {w.name}: N={w.N} dtype={w.dtype}; generating seeded inputs")
+    t0 = time.perf_counter()
+    ic = W.make_inputs(w)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    lat = Lattice(**w.model(), dtype=dtype, device="cuda:0")
+    dev = [torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")]
+    ad0 = lat.init_physical(*dev, ic["a0"])
+    del dev
+    torch.cuda.synchronize()
+    log(f"initialised, a'(0) = {ad0:.6f}; warmup {args.warmup} steps")
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = lat.last_step_ms()
+    ms_per_step = ev_ms / args.steps
+    value = w.sites / (ms_per_step * 1e-3) / 1e9
+    log(f"{ms_per_step:.4f} ms/step (events), wall {wall * 1e3 / args.steps:.4f} ms/step, "
+        f"{value:.2f} Gsite-updates/s")
+    en = lat.energies()
+    log(f"energies after {en['step']} steps: a={en['a']:.6f} R={en['R']:.3e}")
+
+    kms = lat.time_kernels(args.kernel_steps)
+    sweep_ms = kms[1]
+    alg_bytes = 8 * esize * w.sites  # read f, v; write v, f_new; two fields
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name)
+    log(f"kernel ms: a-update {kms[0]:.4f}, sweep {sweep_ms:.4f}, reduce {kms[2]:.4f}; "
+        f"sweep {achieved:.0f} GB/s")
+    lat.close()
+    torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host (bounded sample)")
+        cpu = cpu_baseline(w, ic)
+        log(f"cpu baseline {cpu['value']:.4f} Gsite-updates/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gsite-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: m^2 phi^2 + g^2 phi^2 chi^2 (G=2.5e5), {w.N}^3 periodic, "
+                               f"L={w.L}, dt={w.dt}, vacuum fluctuations, seed [3,0,i,k]",
+                   "N": w.N, "sites": w.sites, "lattice_dtype": w.dtype,
+                   "step_hbm_frac_algorithmic": round(value * 1e9 * 8 * esize / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_sweep (fused kick-drift)",
+                     "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

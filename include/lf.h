@@ -1,0 +1,199 @@
+/*
+ * lf.h — C ABI of the MI355X (gfx950) FRW lattice leapfrog library, liblf.so.
+ *
+ * The library evolves two interacting scalar fields f1 (inflaton, phi) and f2
+ * (chi) on a periodic N^3 lattice in an expanding Friedmann–Robertson–Walker
+ * background with the staggered leapfrog of J. Sainio, "CUDAEASY — a GPU
+ * Accelerated Cosmological Lattice Program" (arXiv:0911.5692), Sec. II.B:
+ *
+ *   field equation, program units, eq. (scalar-evo):
+ *     f_i'' = a^(-2s-2) Lap f_i + [r(s-r+2)(a'/a)^2 + r a''/a] f_i - dV_pr/df_i
+ *   scale factor, eq. (scale):
+ *     a'' = (-s-2) a'^2/a + kappa^2 a^(-2s-2r-1) < sum_i |grad f_i|^2/3 + a^(2s+2) V_pr >
+ *   leapfrog, eq. (evo): f at half-integer steps, f' and a' at integer steps.
+ *
+ * Model family (program units, Sec. II.B and Sec. III):
+ *     V_pr = c1 a^p1 f1^beta / beta + G a^p2 f1^2 f2^2 / 2,
+ *     p1 = -2s + (2-beta) r,  p2 = -2s - 2r,  with s - 2r + 3 = 0.
+ *   lambda phi^4: beta = 4, r = 1, s = -1.   m^2 phi^2: beta = 2, r = 3/2, s = 0.
+ *
+ * The Laplacian is the 7-point (6-neighbour) stencil, periodic in x, y, z
+ * (the LATTICEEASY discretisation named in Sec. II.C).
+ *
+ * Layout.  Every lattice array is N^3 contiguous elements, x fastest:
+ * element (x, y, z) sits at (z*N + y)*N + x.  Arrays are device pointers,
+ * 256-byte aligned, in the element type the call names (float or double).
+ *
+ * Precision.  dtype LF_F32 stores the fields and evaluates the stencil in
+ * FP32; LF_F64 does both in FP64.  In both cases the device keeps the
+ * spatially homogeneous mode of each field and velocity (the "background",
+ * f_bar_i, v_bar_i) in FP64 and the lattice arrays hold the deviation from it;
+ * the background follows the same leapfrog map as every site, so
+ * f = f_bar + deviation holds exactly in exact arithmetic.  The scale factor,
+ * the background and every volume average are FP64 (sums accumulated in FP64
+ * in a fixed order: results are bitwise reproducible for a given N, dtype and
+ * tile shape).
+ *
+ * Ownership.  The caller allocates every device buffer (inputs, outputs and
+ * the workspace sized by lf_workspace_bytes) and keeps it alive until
+ * lf_destroy; a context owns only host-side state and the HIP graphs it
+ * captured.  A context is not thread-safe: use one context per stream.
+ *
+ * Errors.  Every call returns an lf_status.  No C++ exception crosses the
+ * ABI.  lf_last_error() returns a thread-local message for the last failure.
+ * LF_ENONFINITE is sticky: once a NaN/Inf reaches a volume average or the
+ * scale-factor quadratic, every later lf_energies/lf_ens_energies reports it.
+ */
+#ifndef LF_H
+#define LF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LF_ABI_VERSION 1
+
+typedef enum lf_status {
+    LF_OK = 0,
+    LF_EINVAL = 1,      /* invalid argument (sizes, pointers, parameters) */
+    LF_EHIP = 2,        /* a HIP runtime call failed; message has the HIP error */
+    LF_ENONFINITE = 3,  /* a NaN/Inf reached the averages (sticky) */
+    LF_ESTATE = 4,      /* call out of order (e.g. lf_step before lf_init) */
+    LF_ENOMEM = 5       /* workspace smaller than lf_workspace_bytes */
+} lf_status;
+
+typedef enum lf_dtype { LF_F32 = 0, LF_F64 = 1 } lf_dtype;
+
+/* Lattice, model and launch parameters (copied at create). */
+typedef struct lf_params {
+    int32_t N;        /* sites per side, 4 <= N <= 2048 */
+    int32_t dtype;    /* lf_dtype of the lattice arrays */
+    double L;         /* comoving box side, program units; dx = L/N */
+    double dt;        /* program time step, > 0 */
+    int32_t beta;     /* exponent of the dominant term, 2 <= beta <= 6 */
+    int32_t flags;    /* must be 0 */
+    double c1;        /* program-unit coupling of c1 f1^beta / beta */
+    double G;         /* program-unit g^2 of G f1^2 f2^2 / 2 */
+    double r, s;      /* rescaling exponents; |s - 2r + 3| <= 1e-12 */
+    double kappa2;    /* 8 pi G_Newton / A^2 (0 = no expansion) */
+    int32_t tile_y;   /* rows per tile of the sweep, 0 = automatic */
+    int32_t zchunk;   /* planes per z-chunk of the sweep, 0 = automatic */
+} lf_params;
+
+/* Volume averages at the synchronised time k (eq. rho-pres in program
+ * units): f(k) = f(k+1/2) - dt/2 v(k), a_k = a_{k+1/2} - dt/2 a'_k,
+ *   K_i  = < (v_i - r (a'/a) f_i)^2 / 2 >     kinetic
+ *   Gr_i = < a^(-2s-2) |grad+ f_i|^2 / 2 >    gradient (forward differences)
+ *   P    = < V_pr(f, a) >                      potential
+ *   rho  = sum K + sum Gr + P
+ *   R    = (kappa^2/3) a^(2-2r) rho / a'^2 - 1 Friedmann residual, the
+ *          program-unit form of K/(a^2 H^2) of Sec. III (0 when kappa2 = 0). */
+typedef struct lf_report {
+    int64_t step;
+    double a, ad, hubble;   /* a_k, a'_k, a'_k / a_k */
+    double K[2], Gr[2], P, rho, R;
+    uint32_t status;        /* nonzero: a NaN/Inf was seen (sticky) */
+    uint32_t pad_;
+} lf_report;
+
+/* Scalar part of a checkpoint (see lf_get_state). */
+typedef struct lf_scalars {
+    int64_t step;
+    double a_half;      /* a_{k+1/2} */
+    double ad;          /* a'_k */
+    double bg_f[2];     /* background f_bar_i(k+1/2) */
+    double bg_v[2];     /* background v_bar_i(k) */
+    double pend[4];     /* sums over the stored f(k+1/2) that the next step's
+                           a'' needs: sum|grad+ f1|^2 dx^2, same for f2,
+                           sum f1^beta, sum f1^2 f2^2 */
+    uint32_t status;
+    uint32_t pad_;
+} lf_scalars;
+
+typedef struct lf_ctx lf_ctx;
+typedef struct lf_ens lf_ens;
+
+/* ---- version and errors ------------------------------------------------ */
+
+int lf_abi_version(void);
+/* Thread-local, valid until the next failing call on this thread. */
+const char *lf_last_error(void);
+
+/* ---- single lattice ---------------------------------------------------- */
+
+/* Bytes of device workspace a context with these parameters needs.
+ * EINVAL if the parameters are invalid. */
+int lf_workspace_bytes(const lf_params *p, size_t *out_bytes);
+
+/* Create a context.  stream: a hipStream_t (NULL = the null stream) on which
+ * every later call enqueues its work; workspace: device memory of at least
+ * lf_workspace_bytes bytes, 256-byte aligned, owned by the caller.
+ * EINVAL (parameters, alignment, NULL workspace), ENOMEM (too small). */
+int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes,
+              lf_ctx **out);
+
+/* Destroy a context; frees host state and graphs only.  NULL is a no-op. */
+int lf_destroy(lf_ctx *ctx);
+
+/* Initialise from a synchronised program-unit state at tau = 0
+ * (Sec. II.B): fields f1, f2 and velocities v1 = f1', v2 = f2', N^3 device
+ * arrays of element type in_dtype (read only; may be freed after the call
+ * returns and the stream has run), scale factor a0 > 0 and a'_0 = ad0.
+ * Computes the background (the FP64 spatial means), writes the deviations
+ * into the workspace and advances the fields half a step (the
+ * desynchronisation of Sec. II.B).  Asynchronous on the context's stream. */
+int lf_init(lf_ctx *ctx, const void *f1, const void *f2, const void *v1, const void *v2,
+            int in_dtype, double a0, double ad0);
+
+/* Initialise from fields and rescaled physical velocities
+ * u_i = (A/B) a^(r-s) dphi_i/dt (Sec. II.B, conversion to program units):
+ * a'_0 > 0 follows from the Friedmann constraint
+ *   a'^2 = (kappa^2/3) a^(2-2r) < sum_i u_i^2/2 + a^(-2s-2)|grad+ f_i|^2/2 + V_pr >
+ * and v_i = u_i + r (a'_0/a_0) f_i.  Blocking (returns a'_0 in *ad0_out). */
+int lf_init_physical(lf_ctx *ctx, const void *f1, const void *f2, const void *u1,
+                     const void *u2, int in_dtype, double a0, double *ad0_out);
+
+/* Enqueue n >= 0 leapfrog steps (hipGraph replay; asynchronous).
+ * ESTATE before lf_init. */
+int lf_step(lf_ctx *ctx, int64_t n);
+
+/* Blocking: volume averages at the current synchronised time. Returns
+ * ENONFINITE (after filling *out) if the sticky flag is set. */
+int lf_energies(lf_ctx *ctx, lf_report *out);
+
+/* Write the full fields (background + deviation) to caller arrays of element
+ * type out_dtype: synchronized = 0 gives the stored f(k+1/2), v(k);
+ * synchronized = 1 gives f(k) = f(k+1/2) - dt/2 v(k), v(k).  Any pointer may
+ * be NULL (skipped).  Asynchronous. */
+int lf_get_fields(lf_ctx *ctx, void *f1, void *f2, void *v1, void *v2, int out_dtype,
+                  int synchronized);
+
+/* Bitwise checkpoint: copy the four deviation arrays (context dtype) to the
+ * caller and return the scalars (blocking).  lf_set_state restores them into a
+ * context with the same parameters; evolution then continues bitwise as if
+ * uninterrupted. */
+int lf_get_state(lf_ctx *ctx, void *d1, void *d2, void *e1, void *e2, lf_scalars *s);
+int lf_set_state(lf_ctx *ctx, const void *d1, const void *d2, const void *e1,
+                 const void *e2, const lf_scalars *s);
+
+/* Change G (the program-unit g^2) for later steps. */
+int lf_set_coupling(lf_ctx *ctx, double G);
+
+/* Time of the last lf_step call measured with HIP events around the work it
+ * enqueued, in ms (blocking; 0 if none). */
+int lf_last_step_ms(lf_ctx *ctx, double *ms);
+
+/* Measurement: run n >= 1 steps outside any graph with HIP events around
+ * each kernel of the step (on the context's stream) and return the average
+ * duration in ms of kernel j in ms[j], j < n_out:
+ *   0 = scale-factor update, 1 = kick-drift sweep, 2 = separate reduction
+ *   (0 when the sweep computes it in-sweep).  Blocking.  Advances the state. */
+int lf_time_kernels(lf_ctx *ctx, int64_t n, double *ms, int n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LF_H */

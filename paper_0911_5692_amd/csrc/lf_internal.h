@@ -1,0 +1,81 @@
+// Internal declarations shared by the kernels and the C-ABI layer of liblf.
+// Equation references: Sainio, "CUDAEASY", arXiv:0911.5692, Sec. II.B.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf {
+
+constexpr int kMaxBeta = 6;
+constexpr int kNPart = 4;   // step reduction: sum|d+ f1|^2, sum|d+ f2|^2, sum f1^beta, sum f1^2 f2^2
+constexpr int kNMom = 10;   // input moments (see k_input_moments)
+constexpr int kNEn = 6;     // energy sums (see k_energy_part)
+constexpr int kStage2Threads = 256;
+
+// Model parameters in device memory (read by the scale-factor kernel, so a
+// captured graph picks up lf_set_coupling without re-capture).
+struct DevParams {
+    double L, dx, dt, c1, G, r, s, kappa2;
+    double p1, p2;      // powers of a of the degree-beta and degree-4 terms of V_pr
+    int N, beta;
+    double N3;          // N^3 as a double
+};
+
+// FP64 scalar state of the evolution (device resident).
+struct DevScalars {
+    double a_half;      // a_{k+1/2}
+    double ad;          // a'_k
+    double bg_f[2];     // homogeneous mode f_bar_i(k+1/2)
+    double bg_v[2];     // homogeneous mode v_bar_i(k)
+    double pend[kNPart];// totals of the last step reduction (over the stored f)
+    long long step;
+    unsigned int status;// bit 0: non-finite average / quadratic
+    unsigned int pad;
+    // initialisation scratch
+    double mean_f[2], mean_u[2], conv, ad0;
+};
+
+// Per-step coefficients of the fused kick-drift, written by the scale-factor
+// kernel in both precisions (the sweep reads its own).
+template <typename T>
+struct Coef {
+    T Cl;        // dt a^(-2s-2) / dx^2  (multiplies the raw 6-neighbour sum)
+    T Cf;        // dt [r(s-r+2)(a'/a)^2 + r a''/a]
+    T dt;
+    T C2;        // dt G a^p2
+    T g1, g2;    // background f_bar at k+1/2
+    T two_g1, two_g2, g1sq;
+    T h[kMaxBeta];  // dt c1 a^p1 C(beta-1, j) g1^(beta-1-j), j = 1..beta-1 (h[j-1])
+    int nh;         // beta - 1
+    int pad;
+};
+
+struct CoefPair {
+    Coef<float> f;
+    Coef<double> d;
+    double g1n, g2n;    // background at k+3/2 (FP64), for the reduction of f_new
+};
+
+// Launch helpers (lf_kernels.hip).  All enqueue on `st`.
+void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
+                          const void *v2, int N, int beta, double *part, int nblk, hipStream_t st);
+void launch_init_scalars(const double *part, int nblk, const DevParams *P, DevScalars *S,
+                         int physical, double a0, double ad0, hipStream_t st);
+void launch_init_fields(int dtype, int in_dtype, const void *f1, const void *f2, const void *v1,
+                        const void *v2, void *d1, void *d2, void *e1, void *e2, int N,
+                        const DevParams *P, const DevScalars *S, hipStream_t st);
+void launch_reduce(int dtype, const void *d1, const void *d2, int N, const double *bg_f,
+                   int beta, double *part, int nblk, hipStream_t st);
+void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S,
+                    CoefPair *C, hipStream_t st);
+void launch_sweep_plain(int dtype, const void *const in[4], void *const out[4], int N,
+                        const CoefPair *C, hipStream_t st);
+void launch_energy(int dtype, const void *const st4[4], int N, const DevParams *P,
+                   const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st);
+void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],
+                       int N, const DevParams *P, const DevScalars *S, int synchronized,
+                       hipStream_t st);
+void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st);
+void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st);
+
+}  // namespace lf

@@ -1,0 +1,511 @@
+// Device kernels of liblf for gfx950 (CDNA4): initialisation, the FP64
+// scale-factor update, reductions, energies and field export.  The fused
+// kick-drift sweep lives in lf_sweep.hip.
+//
+// Equation references: Sainio, "CUDAEASY", arXiv:0911.5692, Sec. II.B.
+#include "lf_internal.h"
+
+#include <math.h>
+
+namespace lf {
+
+// ---------------------------------------------------------------- helpers
+
+// Sum NV per-thread doubles over the block in a fixed order (wave butterfly,
+// then waves in index order) and store the NV totals at out.  Deterministic.
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double *out)
+{
+    __shared__ double sm[NV][16];
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = t & 63, wave = t >> 6, nw = (nthreads + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sm[i][wave] = v[i];
+    }
+    __syncthreads();
+    if (t < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sm[t][w];
+        out[t] = s;
+    }
+}
+
+// Stage 2 of every reduction: one block of kStage2Threads sums nblk rows of
+// nv partials in a fixed order.  Result in `tot` (valid in thread 0 after the
+// call; all threads see it through shared memory).
+template <int NV>
+__device__ inline void stage2_sum(const double *part, int nblk, double (&tot)[NV])
+{
+    __shared__ double res[NV];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)j * NV + i];
+    }
+    block_sum_store<NV>(acc, res);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = res[i];
+}
+
+__device__ inline double ipow_d(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+__device__ inline void site_xyz(int64_t i, int N, int &x, int &y, int &z)
+{
+    x = (int)(i % N);
+    int64_t t = i / N;
+    y = (int)(t % N);
+    z = (int)(t / N);
+}
+
+// ---------------------------------------------------------------- init
+
+// Moments of an input state (element type Tin), FP64 per site:
+//  0,1: sum f_i   2,3: sum u_i   4,5: sum u_i^2   6,7: sum |d+ f_i|^2 (no 1/dx^2)
+//  8: sum f1^beta   9: sum f1^2 f2^2
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_input_moments(const Tin *__restrict__ f1, const Tin *__restrict__ f2,
+                                                       const Tin *__restrict__ u1, const Tin *__restrict__ u2,
+                                                       int N, int beta, double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const int64_t NN = (int64_t)N * N;
+    double acc[kNMom];
+#pragma unroll
+    for (int i = 0; i < kNMom; ++i) acc[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(i, N, x, y, z);
+        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
+        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
+        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const double a = (double)f1[i], b = (double)f2[i];
+        const double p = (double)u1[i], q = (double)u2[i];
+        acc[0] += a; acc[1] += b; acc[2] += p; acc[3] += q;
+        acc[4] += p * p; acc[5] += q * q;
+        double t0 = (double)f1[ix] - a, t1 = (double)f1[iy] - a, t2 = (double)f1[iz] - a;
+        acc[6] += t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = (double)f2[ix] - b; t1 = (double)f2[iy] - b; t2 = (double)f2[iz] - b;
+        acc[7] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[8] += ipow_d(a, beta);
+        acc[9] += a * a * b * b;
+    }
+    block_sum_store<kNMom>(acc, part + (size_t)blockIdx.x * kNMom);
+}
+
+// Background, scale factor and (physical = 1) the Friedmann a'_0 of the
+// initial state (Sec. II.B: conversion to program units, desynchronisation).
+__global__ void __launch_bounds__(kStage2Threads) k_init_scalars(const double *part, int nblk,
+                                                                 const DevParams *__restrict__ P,
+                                                                 DevScalars *S, int physical,
+                                                                 double a0, double ad0)
+{
+    double m[kNMom];
+    stage2_sum<kNMom>(part, nblk, m);
+    if (threadIdx.x != 0) return;
+    const double N3 = P->N3, r = P->r, s = P->s;
+    const double mf1 = m[0] / N3, mf2 = m[1] / N3, mu1 = m[2] / N3, mu2 = m[3] / N3;
+    double conv = 0.0;
+    unsigned int bad = 0;
+    for (int i = 0; i < kNMom; ++i) bad |= !isfinite(m[i]);
+    if (physical) {
+        // a'^2 = (kappa^2/3) a^(2-2r) rho_pr with physical velocities u
+        const double rho = (0.5 * (m[4] + m[5])
+                            + 0.5 * pow(a0, -2.0 * s - 2.0) * (m[6] + m[7]) / (P->dx * P->dx)
+                            + P->c1 * pow(a0, P->p1) * m[8] / (double)P->beta
+                            + 0.5 * P->G * pow(a0, P->p2) * m[9]) / N3;
+        const double q = (P->kappa2 / 3.0) * pow(a0, 2.0 - 2.0 * r) * rho;
+        bad |= !(q >= 0.0);
+        ad0 = sqrt(q);
+        conv = r * ad0 / a0;
+    }
+    const double vb1 = mu1 + conv * mf1, vb2 = mu2 + conv * mf2;
+    const double h = 0.5 * P->dt;
+    S->mean_f[0] = mf1; S->mean_f[1] = mf2;
+    S->mean_u[0] = mu1; S->mean_u[1] = mu2;
+    S->conv = conv;
+    S->ad0 = ad0;
+    S->bg_f[0] = mf1 + h * vb1;
+    S->bg_f[1] = mf2 + h * vb2;
+    S->bg_v[0] = vb1;
+    S->bg_v[1] = vb2;
+    S->a_half = a0 + h * ad0;
+    S->ad = ad0;
+    S->step = 0;
+    S->status = bad;
+}
+
+// Deviations from the background at tau = 0, desynchronised by dt/2:
+//   e = (u - u_bar) + conv (f - f_bar),  d = (f - f_bar) + dt/2 e.
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(256) k_init_fields(const Tin *__restrict__ f1, const Tin *__restrict__ f2,
+                                                     const Tin *__restrict__ u1, const Tin *__restrict__ u2,
+                                                     T *d1, T *d2, T *e1, T *e2, int N,
+                                                     const DevParams *__restrict__ P,
+                                                     const DevScalars *__restrict__ S)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const double h = 0.5 * P->dt, conv = S->conv;
+    const double mf1 = S->mean_f[0], mf2 = S->mean_f[1], mu1 = S->mean_u[0], mu2 = S->mean_u[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)f1[i] - mf1, b = (double)f2[i] - mf2;
+        const double p = ((double)u1[i] - mu1) + conv * a;
+        const double q = ((double)u2[i] - mu2) + conv * b;
+        d1[i] = (T)(a + h * p);
+        d2[i] = (T)(b + h * q);
+        e1[i] = (T)p;
+        e2[i] = (T)q;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sums over the stored fields that the next scale-factor update needs
+// (eq. scale): sum |d+ f_i|^2 (raw differences, no 1/dx^2), sum f1^beta and
+// sum f1^2 f2^2 with f = f_bar + d evaluated in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce(const T *__restrict__ d1, const T *__restrict__ d2, int N,
+                                                const double *__restrict__ bg_f, int beta, double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const int64_t NN = (int64_t)N * N;
+    const double g1 = bg_f[0], g2 = bg_f[1];
+    double acc[kNPart] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(i, N, x, y, z);
+        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
+        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
+        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const double a = (double)d1[i], b = (double)d2[i];
+        double t0 = (double)d1[ix] - a, t1 = (double)d1[iy] - a, t2 = (double)d1[iz] - a;
+        acc[0] += t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = (double)d2[ix] - b; t1 = (double)d2[iy] - b; t2 = (double)d2[iz] - b;
+        acc[1] += t0 * t0 + t1 * t1 + t2 * t2;
+        const double x1 = g1 + a, x2 = g2 + b;
+        acc[2] += ipow_d(x1, beta);
+        acc[3] += x1 * x1 * x2 * x2;
+    }
+    block_sum_store<kNPart>(acc, part + (size_t)blockIdx.x * kNPart);
+}
+
+__global__ void __launch_bounds__(kStage2Threads) k_sum_partials4(const double *part, int nblk, double *out)
+{
+    double t[kNPart];
+    stage2_sum<kNPart>(part, nblk, t);
+    if (threadIdx.x < kNPart) out[threadIdx.x] = t[threadIdx.x];
+}
+
+// Install checkpointed totals as the pending partials: row 0 holds the
+// totals, the other rows zero, so the fixed-order stage 2 returns them
+// bitwise.
+__global__ void k_set_pending(double *part, int nblk, const double *tot)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nblk * kNPart;
+         j += gridDim.x * blockDim.x)
+        part[j] = (j < kNPart) ? tot[j] : 0.0;
+}
+
+// ---------------------------------------------------------------- a-update
+
+__device__ inline double binom_d(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+// One step of the scale factor and the homogeneous mode, in FP64, and the
+// coefficients of the fused kick-drift (eq. scale, eq. scalar-evo, eq. evo).
+// State on entry: a_{k+1/2}, a'_k, background f_bar(k+1/2), v_bar(k), and
+// the partial sums over f(k+1/2).
+//   F_a = kappa^2 a^(-2s-2r-1) [Sg/3 + a^(2s+2) SV]
+//   a'_{k+1} solves a'_{k+1} = a'_k + dt[(-s-2)((a'_k + a'_{k+1})/2)^2/a + F_a]
+//     (time-centred; the root that tends to a'_k + dt F_a as the quadratic
+//      coefficient vanishes, written in the cancellation-free form)
+//   a'_{k+1/2} = (a'_k + a'_{k+1})/2, a''_{k+1/2} = (a'_{k+1} - a'_k)/dt,
+//   a_{k+3/2} = a_{k+1/2} + dt a'_{k+1}.
+__global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, int nblk,
+                                                            const DevParams *__restrict__ P,
+                                                            DevScalars *S, CoefPair *C)
+{
+    double t[kNPart];
+    stage2_sum<kNPart>(part, nblk, t);
+    if (threadIdx.x != 0) return;
+    const double N3 = P->N3, dx = P->dx, dt = P->dt, r = P->r, s = P->s;
+    const double c1 = P->c1, G = P->G;
+    const int beta = P->beta;
+    const double a = S->a_half, w = S->ad;
+    const double ap1 = pow(a, P->p1), ap2 = pow(a, P->p2);
+    const double Sg = (t[0] + t[1]) / (dx * dx * N3);
+    const double SV = (c1 * ap1 * t[2] / (double)beta + 0.5 * G * ap2 * t[3]) / N3;
+    const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
+    const double c = (-s - 2.0) * dt / (4.0 * a);
+    const double disc = 1.0 - 8.0 * c * w - 4.0 * c * dt * Fa;
+    const double u = 2.0 * (c * w * w + w + dt * Fa) / ((1.0 - 2.0 * c * w) + sqrt(disc));
+    const double adh = 0.5 * (w + u), add = (u - w) / dt, an = a + dt * u;
+    const double alpha = pow(a, -2.0 * s - 2.0);
+    const double bc = r * (s - r + 2.0) * (adh / a) * (adh / a) + r * add / a;
+
+    // homogeneous mode: same kick and drift with zero Laplacian
+    const double g1 = S->bg_f[0], g2 = S->bg_f[1];
+    const double dV1 = c1 * ap1 * ipow_d(g1, beta - 1) + G * ap2 * g1 * g2 * g2;
+    const double dV2 = G * ap2 * g1 * g1 * g2;
+    const double vb1 = S->bg_v[0] + dt * (bc * g1 - dV1);
+    const double vb2 = S->bg_v[1] + dt * (bc * g2 - dV2);
+    const double g1n = g1 + dt * vb1, g2n = g2 + dt * vb2;
+
+    // coefficients at k+1/2
+    double h[kMaxBeta];
+    for (int j = 0; j < kMaxBeta; ++j) h[j] = 0.0;
+    for (int j = 1; j <= beta - 1; ++j)
+        h[j - 1] = dt * c1 * ap1 * binom_d(beta - 1, j) * ipow_d(g1, beta - 1 - j);
+    const double Cl = dt * alpha / (dx * dx), Cf = dt * bc, C2 = dt * G * ap2;
+    Coef<double> &cd = C->d;
+    Coef<float> &cf = C->f;
+    cd.Cl = Cl; cd.Cf = Cf; cd.dt = dt; cd.C2 = C2; cd.g1 = g1; cd.g2 = g2;
+    cd.two_g1 = 2.0 * g1; cd.two_g2 = 2.0 * g2; cd.g1sq = g1 * g1; cd.nh = beta - 1;
+    cf.Cl = (float)Cl; cf.Cf = (float)Cf; cf.dt = (float)dt; cf.C2 = (float)C2;
+    cf.g1 = (float)g1; cf.g2 = (float)g2; cf.two_g1 = (float)(2.0 * g1);
+    cf.two_g2 = (float)(2.0 * g2); cf.g1sq = (float)(g1 * g1); cf.nh = beta - 1;
+    for (int j = 0; j < kMaxBeta; ++j) { cd.h[j] = h[j]; cf.h[j] = (float)h[j]; }
+    C->g1n = g1n;
+    C->g2n = g2n;
+
+    unsigned int bad = 0;
+    for (int i = 0; i < kNPart; ++i) bad |= !isfinite(t[i]);
+    bad |= !(disc >= 0.0) || !isfinite(u);
+    S->status |= bad;
+    for (int i = 0; i < kNPart; ++i) S->pend[i] = t[i];
+    S->a_half = an;
+    S->ad = u;
+    S->bg_f[0] = g1n; S->bg_f[1] = g2n;
+    S->bg_v[0] = vb1; S->bg_v[1] = vb2;
+    S->step += 1;
+}
+
+// ---------------------------------------------------------------- energies
+
+// Per-block sums at the synchronised time (FP64 per site):
+//  0,1: sum (v_i - r (a'/a) f_i)^2   2,3: sum |d+ f_i|^2 (raw)
+//  4: sum f1^beta   5: sum f1^2 f2^2
+template <typename T>
+__global__ void __launch_bounds__(256) k_energy_part(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                     const T *__restrict__ e1, const T *__restrict__ e2,
+                                                     int N, const DevParams *__restrict__ P,
+                                                     const DevScalars *__restrict__ S, double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const int64_t NN = (int64_t)N * N;
+    const double h = 0.5 * P->dt, r = P->r;
+    const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
+    const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
+    const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
+    const int beta = P->beta;
+    double acc[kNEn];
+#pragma unroll
+    for (int i = 0; i < kNEn; ++i) acc[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(i, N, x, y, z);
+        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
+        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
+        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        // synchronised deviations d(k) = d(k+1/2) - dt/2 e(k)
+        const double s1 = (double)d1[i] - h * (double)e1[i];
+        const double s2 = (double)d2[i] - h * (double)e2[i];
+        const double x1 = gs1 + s1, x2 = gs2 + s2;
+        const double q1 = (vb1 + (double)e1[i]) - r * hub * x1;
+        const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
+        acc[0] += q1 * q1;
+        acc[1] += q2 * q2;
+        double t0 = ((double)d1[ix] - h * (double)e1[ix]) - s1;
+        double t1 = ((double)d1[iy] - h * (double)e1[iy]) - s1;
+        double t2 = ((double)d1[iz] - h * (double)e1[iz]) - s1;
+        acc[2] += t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = ((double)d2[ix] - h * (double)e2[ix]) - s2;
+        t1 = ((double)d2[iy] - h * (double)e2[iy]) - s2;
+        t2 = ((double)d2[iz] - h * (double)e2[iz]) - s2;
+        acc[3] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[4] += ipow_d(x1, beta);
+        acc[5] += x1 * x1 * x2 * x2;
+    }
+    block_sum_store<kNEn>(acc, part + (size_t)blockIdx.x * kNEn);
+}
+
+// out: step, a, a', a'/a, K1, K2, G1, G2, P, rho, R, status (as double)
+__global__ void __launch_bounds__(kStage2Threads) k_energy_final(const double *part, int nblk,
+                                                                 const DevParams *__restrict__ P,
+                                                                 const DevScalars *__restrict__ S,
+                                                                 double *out)
+{
+    double t[kNEn];
+    stage2_sum<kNEn>(part, nblk, t);
+    if (threadIdx.x != 0) return;
+    const double N3 = P->N3, h = 0.5 * P->dt, s = P->s, r = P->r;
+    const double ak = S->a_half - h * S->ad, ad = S->ad;
+    const double K1 = 0.5 * t[0] / N3, K2 = 0.5 * t[1] / N3;
+    const double gf = 0.5 * pow(ak, -2.0 * s - 2.0) / (P->dx * P->dx * N3);
+    const double G1 = gf * t[2], G2 = gf * t[3];
+    const double Pv = (P->c1 * pow(ak, P->p1) * t[4] / (double)P->beta + 0.5 * P->G * pow(ak, P->p2) * t[5]) / N3;
+    const double rho = K1 + K2 + G1 + G2 + Pv;
+    const double R = (P->kappa2 / 3.0) * pow(ak, 2.0 - 2.0 * r) * rho / (ad * ad) - 1.0;
+    unsigned int bad = S->status;
+    for (int i = 0; i < kNEn; ++i) bad |= !isfinite(t[i]);
+    out[0] = (double)S->step; out[1] = ak; out[2] = ad; out[3] = ad / ak;
+    out[4] = K1; out[5] = K2; out[6] = G1; out[7] = G2; out[8] = Pv; out[9] = rho;
+    out[10] = (P->kappa2 > 0.0) ? R : 0.0;
+    out[11] = (double)bad;
+}
+
+// ---------------------------------------------------------------- export
+
+template <typename T, typename To>
+__global__ void __launch_bounds__(256) k_get_fields(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                    const T *__restrict__ e1, const T *__restrict__ e2,
+                                                    To *f1, To *f2, To *v1, To *v2, int N,
+                                                    const DevParams *__restrict__ P,
+                                                    const DevScalars *__restrict__ S, int sync)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const double h = sync ? 0.5 * P->dt : 0.0;
+    const double g1 = S->bg_f[0] - h * S->bg_v[0], g2 = S->bg_f[1] - h * S->bg_v[1];
+    const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double p = (double)e1[i], q = (double)e2[i];
+        if (f1) f1[i] = (To)(g1 + ((double)d1[i] - h * p));
+        if (f2) f2[i] = (To)(g2 + ((double)d2[i] - h * q));
+        if (v1) v1[i] = (To)(vb1 + p);
+        if (v2) v2[i] = (To)(vb2 + q);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int grid_for(int64_t n, int per_block, int cap)
+{
+    int64_t g = (n + per_block - 1) / per_block;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
+                          const void *v2, int N, int beta, double *part, int nblk, hipStream_t st)
+{
+    if (in_dtype == 0)
+        hipLaunchKernelGGL(k_input_moments<float>, dim3(nblk), dim3(256), 0, st, (const float *)f1,
+                           (const float *)f2, (const float *)v1, (const float *)v2, N, beta, part);
+    else
+        hipLaunchKernelGGL(k_input_moments<double>, dim3(nblk), dim3(256), 0, st, (const double *)f1,
+                           (const double *)f2, (const double *)v1, (const double *)v2, N, beta, part);
+}
+
+void launch_init_scalars(const double *part, int nblk, const DevParams *P, DevScalars *S,
+                         int physical, double a0, double ad0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S,
+                       physical, a0, ad0);
+}
+
+template <typename T, typename Tin>
+static void init_fields_t(const void *f1, const void *f2, const void *v1, const void *v2, void *d1,
+                          void *d2, void *e1, void *e2, int N, const DevParams *P,
+                          const DevScalars *S, hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    hipLaunchKernelGGL((k_init_fields<T, Tin>), dim3(grid_for(N3, 256, 65536)), dim3(256), 0, st,
+                       (const Tin *)f1, (const Tin *)f2, (const Tin *)v1, (const Tin *)v2, (T *)d1,
+                       (T *)d2, (T *)e1, (T *)e2, N, P, S);
+}
+
+void launch_init_fields(int dtype, int in_dtype, const void *f1, const void *f2, const void *v1,
+                        const void *v2, void *d1, void *d2, void *e1, void *e2, int N,
+                        const DevParams *P, const DevScalars *S, hipStream_t st)
+{
+    if (dtype == 0 && in_dtype == 0) init_fields_t<float, float>(f1, f2, v1, v2, d1, d2, e1, e2, N, P, S, st);
+    else if (dtype == 0) init_fields_t<float, double>(f1, f2, v1, v2, d1, d2, e1, e2, N, P, S, st);
+    else if (in_dtype == 0) init_fields_t<double, float>(f1, f2, v1, v2, d1, d2, e1, e2, N, P, S, st);
+    else init_fields_t<double, double>(f1, f2, v1, v2, d1, d2, e1, e2, N, P, S, st);
+}
+
+void launch_reduce(int dtype, const void *d1, const void *d2, int N, const double *bg_f, int beta,
+                   double *part, int nblk, hipStream_t st)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_reduce<float>, dim3(nblk), dim3(256), 0, st, (const float *)d1,
+                           (const float *)d2, N, bg_f, beta, part);
+    else
+        hipLaunchKernelGGL(k_reduce<double>, dim3(nblk), dim3(256), 0, st, (const double *)d1,
+                           (const double *)d2, N, bg_f, beta, part);
+}
+
+void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S, CoefPair *C,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_aupdate, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, C);
+}
+
+void launch_energy(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
+                   double *part, int nblk, double *out_dev, hipStream_t st)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_energy_part<float>, dim3(nblk), dim3(256), 0, st, (const float *)s4[0],
+                           (const float *)s4[1], (const float *)s4[2], (const float *)s4[3], N, P, S, part);
+    else
+        hipLaunchKernelGGL(k_energy_part<double>, dim3(nblk), dim3(256), 0, st, (const double *)s4[0],
+                           (const double *)s4[1], (const double *)s4[2], (const double *)s4[3], N, P, S, part);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, out_dev);
+}
+
+template <typename T, typename To>
+static void get_fields_t(const void *const s4[4], void *const o[4], int N, const DevParams *P,
+                         const DevScalars *S, int sync, hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    hipLaunchKernelGGL((k_get_fields<T, To>), dim3(grid_for(N3, 256, 65536)), dim3(256), 0, st,
+                       (const T *)s4[0], (const T *)s4[1], (const T *)s4[2], (const T *)s4[3],
+                       (To *)o[0], (To *)o[1], (To *)o[2], (To *)o[3], N, P, S, sync);
+}
+
+void launch_get_fields(int dtype, int out_dtype, const void *const s4[4], void *const out[4], int N,
+                       const DevParams *P, const DevScalars *S, int synchronized, hipStream_t st)
+{
+    if (dtype == 0 && out_dtype == 0) get_fields_t<float, float>(s4, out, N, P, S, synchronized, st);
+    else if (dtype == 0) get_fields_t<float, double>(s4, out, N, P, S, synchronized, st);
+    else if (out_dtype == 0) get_fields_t<double, float>(s4, out, N, P, S, synchronized, st);
+    else get_fields_t<double, double>(s4, out, N, P, S, synchronized, st);
+}
+
+void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st)
+{
+    (void)nv;
+    hipLaunchKernelGGL(k_sum_partials4, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, out);
+}
+
+void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_pending, dim3(grid_for((int64_t)nblk * kNPart, 256, 1024)), dim3(256), 0,
+                       st, part, nblk, totals);
+}
+
+}  // namespace lf

@@ -1,0 +1,146 @@
+"""Python handle of one lattice context of liblf (C ABI in include/lf.h).
+
+PyTorch provides the device memory (workspace and field tensors) and the
+stream; every step of the evolution runs in liblf's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import LF_F32, LF_F64, Params, Report, Scalars, check, lib
+
+_DT = {torch.float32: LF_F32, torch.float64: LF_F64}
+
+
+def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, shape) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"tensor dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"tensor must be contiguous with shape {tuple(shape)}")
+    if t.data_ptr() % 256:
+        raise ValueError("tensor storage must be 256-byte aligned")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _aligned(t: torch.Tensor) -> torch.Tensor:
+    return t if (t.is_contiguous() and t.data_ptr() % 256 == 0) else t.contiguous().clone()
+
+
+class Lattice:
+    """One N^3 two-field lattice (Sainio, arXiv:0911.5692, Sec. II).
+
+    Parameters are program units: box side L, time step dt, potential
+    V_pr = c1 a^p1 f1^beta/beta + G a^p2 f1^2 f2^2 / 2, rescaling exponents
+    r, s (s - 2r + 3 = 0) and kappa2 = 8 pi G_N / A^2.  dtype is the element
+    type of the lattice arrays (float32 or float64).
+    """
+
+    def __init__(self, N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float,
+                 s: float, kappa2: float, dtype: torch.dtype = torch.float32,
+                 device: str | torch.device = "cuda", tile_y: int = 0, zchunk: int = 0,
+                 stream: torch.cuda.Stream | None = None):
+        if dtype not in _DT:
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.N, self.dtype = int(N), dtype
+        self.device = torch.device(device)
+        self.params = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1),
+                             float(G), float(r), float(s), float(kappa2), int(tile_y), int(zchunk))
+        size = ctypes.c_size_t()
+        check(lib().lf_workspace_bytes(ctypes.byref(self.params), ctypes.byref(size)))
+        self.ws_bytes = size.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        check(lib().lf_create(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._keep = ()
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            lib().lf_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.N, self.N, self.N)
+
+    # ------------------------------------------------------------ init
+    def init(self, f1, f2, v1, v2, a0: float, ad0: float) -> None:
+        """Synchronised program-unit state at tau = 0 (float32 or float64 tensors)."""
+        ts = [_aligned(t) for t in (f1, f2, v1, v2)]
+        dt = ts[0].dtype
+        ptrs = [_dev_ptr(t, dt, self.shape) for t in ts]
+        check(lib().lf_init(self._ctx, *ptrs, _DT[dt], float(a0), float(ad0)))
+        self._keep = ts  # inputs must outlive the enqueued kernels
+        self.stream.synchronize()
+        self._keep = ()
+
+    def init_physical(self, f1, f2, u1, u2, a0: float = 1.0) -> float:
+        """Fields and rescaled physical velocities; returns a'(0) from Friedmann."""
+        ts = [_aligned(t) for t in (f1, f2, u1, u2)]
+        dt = ts[0].dtype
+        ptrs = [_dev_ptr(t, dt, self.shape) for t in ts]
+        ad0 = ctypes.c_double()
+        check(lib().lf_init_physical(self._ctx, *ptrs, _DT[dt], float(a0), ctypes.byref(ad0)))
+        return ad0.value
+
+    # ------------------------------------------------------------ evolution
+    def step(self, n: int = 1) -> None:
+        check(lib().lf_step(self._ctx, int(n)))
+
+    def last_step_ms(self) -> float:
+        ms = ctypes.c_double()
+        check(lib().lf_last_step_ms(self._ctx, ctypes.byref(ms)))
+        return ms.value
+
+    def time_kernels(self, n: int):
+        """Average ms per kernel over n eager steps: (a-update, sweep, reduce)."""
+        ms = (ctypes.c_double * 3)()
+        check(lib().lf_time_kernels(self._ctx, int(n), ms, 3))
+        return tuple(ms)
+
+    def set_coupling(self, G: float) -> None:
+        check(lib().lf_set_coupling(self._ctx, float(G)))
+
+    # ------------------------------------------------------------ outputs
+    def energies(self, check_finite: bool = True) -> dict:
+        rep = Report()
+        rc = lib().lf_energies(self._ctx, ctypes.byref(rep))
+        if check_finite or rc not in (0, 3):
+            check(rc)
+        return dict(step=rep.step, a=rep.a, ad=rep.ad, hubble=rep.hubble, K1=rep.K[0],
+                    K2=rep.K[1], G1=rep.Gr[0], G2=rep.Gr[1], P=rep.P, rho=rep.rho, R=rep.R,
+                    status=rep.status)
+
+    def fields(self, synchronized: bool = False, dtype: torch.dtype = torch.float64):
+        """(f1, f2, v1, v2) as new tensors: f(k+1/2) and v(k), or f(k), v(k)."""
+        out = [torch.empty(self.shape, dtype=dtype, device=self.device) for _ in range(4)]
+        ptrs = [_dev_ptr(t, dtype, self.shape) for t in out]
+        check(lib().lf_get_fields(self._ctx, *ptrs, _DT[dtype], 1 if synchronized else 0))
+        self.stream.synchronize()
+        return tuple(out)
+
+    # ------------------------------------------------------------ checkpoint
+    def get_state(self):
+        """Bitwise checkpoint: (deviation tensors d1, d2, e1, e2, Scalars)."""
+        out = [torch.empty(self.shape, dtype=self.dtype, device=self.device) for _ in range(4)]
+        ptrs = [_dev_ptr(t, self.dtype, self.shape) for t in out]
+        sc = Scalars()
+        check(lib().lf_get_state(self._ctx, *ptrs, ctypes.byref(sc)))
+        return tuple(out), sc
+
+    def set_state(self, arrays, scalars: Scalars) -> None:
+        ptrs = [_dev_ptr(t, self.dtype, self.shape) for t in arrays]
+        check(lib().lf_set_state(self._ctx, *ptrs, ctypes.byref(scalars)))
