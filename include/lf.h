@@ -79,8 +79,12 @@ typedef struct lf_params {
     double G;         /* program-unit g^2 of G f1^2 f2^2 / 2 */
     double r, s;      /* rescaling exponents; |s - 2r + 3| <= 1e-12 */
     double kappa2;    /* 8 pi G_Newton / A^2 (0 = no expansion) */
-    int32_t tile_y;   /* rows per tile of the sweep, 0 = automatic */
-    int32_t zchunk;   /* planes per z-chunk of the sweep, 0 = automatic */
+    int32_t tile_y;   /* sweep tile rows: 0 = automatic, 1 = plain one-site-per-thread
+                         sweep with a separate reduction, 4, 8 or 16 = LDS z-march */
+    int32_t zchunk;   /* planes per z-chunk of the LDS sweep, 0 = automatic */
+    int32_t tile_x;   /* sweep tile columns: 0 = automatic, 64 or 128 (128 with
+                         tile_y 4 or 8 only) */
+    int32_t reserved; /* must be 0 */
 } lf_params;
 
 /* Volume averages at the synchronised time k (eq. rho-pres in program
@@ -185,6 +189,37 @@ int lf_set_coupling(lf_ctx *ctx, double G);
 /* Time of the last lf_step call measured with HIP events around the work it
  * enqueued, in ms (blocking; 0 if none). */
 int lf_last_step_ms(lf_ctx *ctx, double *ms);
+
+/* ---- ensemble of independent lattices --------------------------------- */
+
+/* R realizations evolved together: per_real[r] gives each one's lattice and
+ * model (N, L, dt, couplings may differ; dtype and beta must be equal).
+ * Every step is two launches for the whole ensemble, captured in a HIP
+ * graph: a batched FP64 scale-factor update (one block per realization, each
+ * with its own a(t), background and averages) and one persistent sweep whose
+ * grid walks a static list of (realization, tile, z-chunk) work items.  The
+ * sweep tile is per_real[0].tile_x/tile_y (default 64 x 8) for all
+ * realizations; z-chunks may differ per realization (default 16 planes, 32
+ * above N = 128).  Each realization's state matches a single-lattice run
+ * with the same parameters to rounding. */
+int lf_ens_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
+int lf_ens_create(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,
+                  lf_ens **out);
+int lf_ens_destroy(lf_ens *ens);
+int lf_ens_size(lf_ens *ens, int *R);
+/* As lf_init / lf_init_physical for realization r (only before the first
+ * lf_ens_step, or after an even number of steps). */
+int lf_ens_init(lf_ens *ens, int r, const void *f1, const void *f2, const void *v1,
+                const void *v2, int in_dtype, double a0, double ad0);
+int lf_ens_init_physical(lf_ens *ens, int r, const void *f1, const void *f2, const void *u1,
+                         const void *u2, int in_dtype, double a0, double *ad0_out);
+/* Enqueue n >= 0 steps of every realization (asynchronous). */
+int lf_ens_step(lf_ens *ens, int64_t n);
+int lf_ens_last_step_ms(lf_ens *ens, double *ms);
+/* Blocking: out[r] for r < R; ENONFINITE if any realization has the flag. */
+int lf_ens_energies(lf_ens *ens, lf_report *out);
+int lf_ens_get_fields(lf_ens *ens, int r, void *f1, void *f2, void *v1, void *v2, int out_dtype,
+                      int synchronized);
 
 /* Measurement: run n >= 1 steps outside any graph with HIP events around
  * each kernel of the step (on the context's stream) and return the average

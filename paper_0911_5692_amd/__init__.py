@@ -12,12 +12,12 @@ from __future__ import annotations
 
 import importlib
 
-__all__ = ["Lattice", "LfError", "inputs", "workloads", "build"]
+__all__ = ["Lattice", "Ensemble", "LfError", "inputs", "workloads", "build"]
 
 
 def __getattr__(name):
-    if name == "Lattice":
-        return importlib.import_module(".lattice", __name__).Lattice
+    if name in ("Lattice", "Ensemble"):
+        return getattr(importlib.import_module(".lattice", __name__), name)
     if name == "LfError":
         return importlib.import_module("._lib", __name__).LfError
     if name in ("inputs", "workloads", "build"):

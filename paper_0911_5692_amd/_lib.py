@@ -30,7 +30,7 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("beta", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("c1", ctypes.c_double), ("G", ctypes.c_double), ("r", ctypes.c_double),
                 ("s", ctypes.c_double), ("kappa2", ctypes.c_double), ("tile_y", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -69,6 +69,20 @@ SIGNATURES = {
     "lf_set_coupling": ([_vp, ctypes.c_double], ctypes.c_int),
     "lf_last_step_ms": ([_vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "lf_time_kernels": ([_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "lf_ens_workspace_bytes": ([ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
+                               ctypes.c_int),
+    "lf_ens_create": ([ctypes.c_int, ctypes.POINTER(Params), _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)],
+                      ctypes.c_int),
+    "lf_ens_destroy": ([_vp], ctypes.c_int),
+    "lf_ens_size": ([_vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "lf_ens_init": ([_vp, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double],
+                    ctypes.c_int),
+    "lf_ens_init_physical": ([_vp, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double,
+                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "lf_ens_step": ([_vp, ctypes.c_int64], ctypes.c_int),
+    "lf_ens_last_step_ms": ([_vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "lf_ens_energies": ([_vp, ctypes.POINTER(Report)], ctypes.c_int),
+    "lf_ens_get_fields": ([_vp, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
 }
 
 

@@ -35,7 +35,67 @@ int fail(int code, const char *fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int kRedBlocks = 2048;     // grid of the grid-stride reductions
-constexpr int kMaxPartRows = 65536;  // partial rows reserved for any sweep variant
+
+// Sweep variant and launch shape.  tile_y: 1 = plain one-site-per-thread
+// sweep plus a separate reduction; 4, 8, 16 = LDS z-march with in-sweep
+// reductions (rows per tile); 0 = automatic.  zchunk: planes per block.
+struct Shape {
+    int tile_x, tile_y, zchunk, rows;  // rows: partial-sum rows the step reduction writes
+};
+
+// Automatic launch shape.  Tiles of 128 x 8 for large lattices, narrower ones
+// below.  The z-chunk is chosen so that the whole grid is resident at once
+// (resident blocks = blocks per CU from the occupancy calculator x CU count):
+// all tiles then march their chunks in lockstep and the halo rows a tile
+// shares with its neighbours are still in L2 when they are needed.  The
+// resident count is only queried on a machine with a GPU; elsewhere (and for
+// the workspace size) 3 blocks on 256 CUs is assumed, which only changes the
+// partial-sum row count.
+int resident_blocks(const lf_params *p, int tile_x, int tile_y)
+{
+    int dev = 0, cus = 0;
+    int per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        per_cu = sweep_lds_blocks_per_cu(p->dtype, tile_x, tile_y, p->beta);
+    (void)hipGetLastError();
+    if (per_cu <= 0 || cus <= 0) return 3 * 256;
+    return per_cu * cus;
+}
+
+Shape shape_of(const lf_params *p)
+{
+    Shape sh{};
+    const int N = p->N;
+    if (p->tile_y) {
+        sh.tile_y = p->tile_y;
+        sh.tile_x = p->tile_x ? p->tile_x : 64;
+    } else if (N >= 256) {
+        sh.tile_x = 128;
+        sh.tile_y = 8;
+    } else {
+        sh.tile_x = 64;
+        sh.tile_y = N >= 96 ? 8 : 4;
+    }
+    if (sh.tile_y == 1) {
+        sh.tile_x = 0;
+        sh.zchunk = 0;
+        sh.rows = kRedBlocks;
+        return sh;
+    }
+    if (p->zchunk) {
+        sh.zchunk = p->zchunk < N ? p->zchunk : N;
+    } else {
+        const int per_slab = ((N + sh.tile_x - 1) / sh.tile_x) * ((N + sh.tile_y - 1) / sh.tile_y);
+        int nzc = resident_blocks(p, sh.tile_x, sh.tile_y) / per_slab;
+        nzc = nzc < 1 ? 1 : nzc;
+        int dz = (N + nzc - 1) / nzc;
+        dz = dz < 8 ? 8 : dz;
+        sh.zchunk = dz < N ? dz : N;
+    }
+    sh.rows = sweep_lds_blocks(N, sh.tile_x, sh.tile_y, sh.zchunk);
+    return sh;
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -57,7 +117,7 @@ Layout layout_of(const lf_params *p)
             L.state[b][j] = off;
             off = align_up(off + n3 * esize(p->dtype));
         }
-    L.part = off; off = align_up(off + (size_t)kMaxPartRows * kNPart * sizeof(double));
+    L.part = off; off = align_up(off + (size_t)shape_of(p).rows * kNPart * sizeof(double));
     L.mom = off; off = align_up(off + (size_t)kRedBlocks * kNMom * sizeof(double));
     L.enp = off; off = align_up(off + (size_t)kRedBlocks * kNEn * sizeof(double));
     L.enout = off; off = align_up(off + 16 * sizeof(double));
@@ -83,7 +143,14 @@ int validate(const lf_params *p)
     if (fabs(p->s - 2.0 * p->r + 3.0) > 1e-12)
         return fail(LF_EINVAL, "rescaling exponents violate s - 2r + 3 = 0 (r=%g, s=%g)", p->r, p->s);
     if (!(p->kappa2 >= 0.0) || !isfinite(p->kappa2)) return fail(LF_EINVAL, "kappa2 must be >= 0");
-    if (p->tile_y < 0 || p->zchunk < 0) return fail(LF_EINVAL, "tile_y/zchunk must be >= 0");
+    if (p->tile_y != 0 && p->tile_y != 1 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16)
+        return fail(LF_EINVAL, "tile_y=%d: must be 0 (auto), 1 (plain), 4, 8 or 16", p->tile_y);
+    if (p->zchunk < 0 || p->zchunk > 4096) return fail(LF_EINVAL, "zchunk=%d out of range", p->zchunk);
+    if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 128)
+        return fail(LF_EINVAL, "tile_x=%d: must be 0 (auto), 64 or 128", p->tile_x);
+    if (p->tile_x == 128 && p->tile_y != 4 && p->tile_y != 8)
+        return fail(LF_EINVAL, "tile_x=128 needs tile_y 4 or 8");
+    if (p->reserved != 0) return fail(LF_EINVAL, "reserved must be 0");
     return LF_OK;
 }
 
@@ -92,6 +159,7 @@ int validate(const lf_params *p)
 struct lf_ctx {
     lf_params p;
     Layout L;
+    Shape sh;
     hipStream_t stream;
     hipStream_t cap;
     char *ws;
@@ -111,22 +179,42 @@ struct lf_ctx {
 
 namespace {
 
-int enqueue_step(lf_ctx *c, int cur, hipStream_t st)
+// One leapfrog step: FP64 scale-factor update from the pending partial sums,
+// then the fused kick-drift sweep from buffer `cur` into `cur ^ 1`, which
+// leaves the partial sums of the new fields for the next step.
+void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
 {
     const void *in[4] = {c->buf[cur][0], c->buf[cur][1], c->buf[cur][2], c->buf[cur][3]};
     void *out[4] = {c->buf[cur ^ 1][0], c->buf[cur ^ 1][1], c->buf[cur ^ 1][2], c->buf[cur ^ 1][3]};
-    launch_aupdate(c->part, kRedBlocks, c->P, c->S, c->C, st);
-    launch_sweep_plain(c->p.dtype, in, out, c->p.N, c->C, st);
-    launch_reduce(c->p.dtype, out[0], out[1], c->p.N, c->S->bg_f, c->p.beta, c->part, kRedBlocks, st);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    launch_aupdate(c->part, c->sh.rows, c->P, c->S, c->C, st);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    if (c->sh.tile_y == 1) {
+        launch_sweep_plain(c->p.dtype, c->p.beta, in, out, c->p.N, c->C, st);
+        if (ev) (void)hipEventRecord(ev[2], st);
+        launch_reduce(c->p.dtype, out[0], out[1], c->p.N, c->S->bg_f, c->p.beta, c->part, c->sh.rows, st);
+    } else {
+        launch_sweep_lds(c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, in, out, c->p.N,
+                         c->sh.zchunk, c->C, c->part, st);
+        if (ev) (void)hipEventRecord(ev[2], st);
+    }
+    if (ev) (void)hipEventRecord(ev[3], st);
+}
+
+int ensure_events(hipEvent_t *ev0, hipEvent_t *ev1)
+{
+    if (!*ev0) HIPCHK(hipEventCreate(ev0));
+    if (!*ev1) HIPCHK(hipEventCreate(ev1));
     return LF_OK;
 }
 
 int capture(lf_ctx *c, int nsteps, int start, hipGraphExec_t *exec)
 {
+    if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int cur = start;
     for (int k = 0; k < nsteps; ++k) {
-        enqueue_step(c, cur, c->cap);
+        enqueue_step(c, cur, c->cap, nullptr);
         cur ^= 1;
     }
     hipGraph_t g = nullptr;
@@ -198,6 +286,7 @@ int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes
     if (!c) return fail(LF_ENOMEM, "host allocation failed");
     c->p = *p;
     c->L = L;
+    c->sh = shape_of(p);
     c->stream = (hipStream_t)stream;
     c->ws = (char *)workspace;
     for (int b = 0; b < 2; ++b)
@@ -211,16 +300,7 @@ int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes
     c->S = (DevScalars *)(c->ws + L.S);
     c->C = (CoefPair *)(c->ws + L.C);
     c->K = (p->N >= 256) ? 8 : 32;
-    hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete c;
-        return fail(LF_EHIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
-    }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        (void)hipStreamDestroy(c->cap);
-        delete c;
-        return fail(LF_EHIP, "hipEventCreate failed");
-    }
+    hipError_t e;
     DevParams dp;
     fill_dev_params(p, &dp);
     e = hipMemcpyAsync(c->P, &dp, sizeof dp, hipMemcpyHostToDevice, c->stream);
@@ -264,7 +344,7 @@ static int init_common(lf_ctx *c, const void *f1, const void *f2, const void *v1
     launch_init_fields(c->p.dtype, in_dtype, f1, f2, v1, v2, c->buf[0][0], c->buf[0][1],
                        c->buf[0][2], c->buf[0][3], N, c->P, c->S, c->stream);
     launch_reduce(c->p.dtype, c->buf[0][0], c->buf[0][1], N, c->S->bg_f, c->p.beta, c->part,
-                  kRedBlocks, c->stream);
+                  c->sh.rows, c->stream);
     HIPCHK(hipGetLastError());
     c->cur = 0;
     c->inited = 1;
@@ -300,6 +380,7 @@ int lf_step(lf_ctx *c, int64_t n)
     if (n == 0) return LF_OK;
     int rc;
     if (n >= c->K && !c->gK[c->cur] && (rc = capture(c, c->K, c->cur, &c->gK[c->cur]))) return rc;
+    if ((rc = ensure_events(&c->ev0, &c->ev1))) return rc;
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     while (n >= c->K) {
         HIPCHK(hipGraphLaunch(c->gK[c->cur], c->stream));
@@ -380,7 +461,7 @@ int lf_get_state(lf_ctx *c, void *d1, void *d2, void *e1, void *e2, lf_scalars *
     const size_t bytes = (size_t)c->p.N * c->p.N * c->p.N * esize(c->p.dtype);
     for (int j = 0; j < 4; ++j)
         HIPCHK(hipMemcpyAsync(o[j], c->buf[c->cur][j], bytes, hipMemcpyDeviceToDevice, c->stream));
-    launch_sum_partials(c->part, kRedBlocks, kNPart, c->tot, c->stream);
+    launch_sum_partials(c->part, c->sh.rows, kNPart, c->tot, c->stream);
     HIPCHK(hipGetLastError());
     DevScalars hs;
     double tot[kNPart];
@@ -427,7 +508,7 @@ int lf_set_state(lf_ctx *c, const void *d1, const void *d2, const void *e1, cons
     for (int i = 0; i < kNPart; ++i) tot[i] = s->pend[i];
     HIPCHK(hipMemcpyAsync(c->S, &hs, sizeof hs, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->tot, tot, sizeof tot, hipMemcpyHostToDevice, c->stream));
-    launch_set_pending(c->part, kRedBlocks, c->tot, c->stream);
+    launch_set_pending(c->part, c->sh.rows, c->tot, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     c->cur = 0;
@@ -457,18 +538,8 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
     double acc[3] = {0.0, 0.0, 0.0};
     int rc = LF_OK;
     for (int64_t k = 0; k < n && rc == LF_OK; ++k) {
-        const int cur = c->cur;
-        const void *in[4] = {c->buf[cur][0], c->buf[cur][1], c->buf[cur][2], c->buf[cur][3]};
-        void *out[4] = {c->buf[cur ^ 1][0], c->buf[cur ^ 1][1], c->buf[cur ^ 1][2], c->buf[cur ^ 1][3]};
-        hipError_t e = hipEventRecord(ev[0], c->stream);
-        launch_aupdate(c->part, kRedBlocks, c->P, c->S, c->C, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-        launch_sweep_plain(c->p.dtype, in, out, c->p.N, c->C, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
-        launch_reduce(c->p.dtype, out[0], out[1], c->p.N, c->S->bg_f, c->p.beta, c->part, kRedBlocks,
-                      c->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
-        if (e == hipSuccess) e = hipGetLastError();
+        enqueue_step(c, c->cur, c->stream, ev);
+        hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
         float t;
         for (int j = 0; j < 3 && e == hipSuccess; ++j) {
@@ -482,6 +553,313 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
     if (rc) return rc;
     for (int j = 0; j < n_out; ++j) ms[j] = (j < 3) ? acc[j] / (double)n : 0.0;
     return LF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- ensemble
+
+struct lf_ens {
+    int R;
+    int dtype, beta, tile_x, tile_y;
+    hipStream_t stream, cap;
+    lf_ctx **sub;        // one context per realization, on slices of the workspace
+    EnsEntry *tab;       // device table (workspace)
+    int4 *items;         // device work list (workspace)
+    int nitems, grid;
+    int cur;
+    hipGraphExec_t g2, g1[2];
+    hipEvent_t ev0, ev1;
+    int timed;
+};
+
+namespace {
+
+struct EnsLayout {
+    size_t *sub_off;  // R + 1 offsets
+    size_t tab, items, total;
+    int nitems;
+};
+
+int ens_tile_y(const lf_params *p0) { return p0->tile_y ? p0->tile_y : 8; }
+int ens_tile_x(const lf_params *p0) { return p0->tile_x ? p0->tile_x : 64; }
+
+// Parameters of realization r as its sub-context sees them: the ensemble's
+// common tile, and a z-chunk of 16 planes (32 above 128^3) unless given.
+lf_params ens_sub_params(const lf_params *pr, const lf_params *p0)
+{
+    lf_params q = *pr;
+    q.tile_x = ens_tile_x(p0);
+    q.tile_y = ens_tile_y(p0);
+    if (!q.zchunk) q.zchunk = pr->N > 128 ? 32 : 16;
+    return q;
+}
+
+int ens_validate(int R, const lf_params *per)
+{
+    if (R < 1 || R > 4096) return fail(LF_EINVAL, "R=%d out of range [1, 4096]", R);
+    if (!per) return fail(LF_EINVAL, "per-realization params is NULL");
+    for (int r = 0; r < R; ++r) {
+        int rc = validate(&per[r]);
+        if (rc) return rc;
+        if (per[r].dtype != per[0].dtype || per[r].beta != per[0].beta)
+            return fail(LF_EINVAL, "realization %d: dtype and beta must match realization 0", r);
+        if (per[r].tile_y == 1) return fail(LF_EINVAL, "the ensemble needs an LDS sweep tile (tile_y != 1)");
+    }
+    const int ty = ens_tile_y(&per[0]), tx = ens_tile_x(&per[0]);
+    if (ty == 1 || (tx == 128 && ty != 4 && ty != 8)) return fail(LF_EINVAL, "unsupported ensemble tile");
+    return LF_OK;
+}
+
+size_t ens_layout(int R, const lf_params *per, size_t *sub_off, int *nitems)
+{
+    size_t off = 0;
+    int items = 0;
+    for (int r = 0; r < R; ++r) {
+        lf_params q = ens_sub_params(&per[r], &per[0]);
+        sub_off[r] = off;
+        off = align_up(off + layout_of(&q).total);
+        Shape sh = shape_of(&q);
+        items += sh.rows;
+    }
+    sub_off[R] = off;
+    *nitems = items;
+    return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_ens_workspace_bytes(int R, const lf_params *per, size_t *out_bytes)
+{
+    int rc = ens_validate(R, per);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    size_t *so = new size_t[R + 1];
+    int nitems = 0;
+    size_t off = ens_layout(R, per, so, &nitems);
+    delete[] so;
+    off = align_up(off + (size_t)R * sizeof(EnsEntry));
+    off = align_up(off + (size_t)nitems * sizeof(int4));
+    *out_bytes = off;
+    return LF_OK;
+}
+
+int lf_ens_destroy(lf_ens *e)
+{
+    if (!e) return LF_OK;
+    if (e->sub)
+        for (int r = 0; r < e->R; ++r) lf_destroy(e->sub[r]);
+    delete[] e->sub;
+    if (e->g2) (void)hipGraphExecDestroy(e->g2);
+    for (int b = 0; b < 2; ++b)
+        if (e->g1[b]) (void)hipGraphExecDestroy(e->g1[b]);
+    if (e->cap) (void)hipStreamDestroy(e->cap);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    delete e;
+    return LF_OK;
+}
+
+int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, size_t ws_bytes,
+                  lf_ens **out)
+{
+    int rc = ens_validate(R, per);
+    if (rc) return rc;
+    if (!out) return fail(LF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+    size_t need = 0;
+    if ((rc = lf_ens_workspace_bytes(R, per, &need))) return rc;
+    if (ws_bytes < need) return fail(LF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    lf_ens *e = new (std::nothrow) lf_ens();
+    if (!e) return fail(LF_ENOMEM, "host allocation failed");
+    e->R = R;
+    e->dtype = per[0].dtype;
+    e->beta = per[0].beta;
+    e->tile_x = ens_tile_x(&per[0]);
+    e->tile_y = ens_tile_y(&per[0]);
+    e->stream = (hipStream_t)stream;
+    e->sub = new (std::nothrow) lf_ctx *[R]();
+    size_t *so = new size_t[R + 1];
+    int nitems = 0;
+    size_t off = ens_layout(R, per, so, &nitems);
+    char *ws = (char *)workspace;
+    e->tab = (EnsEntry *)(ws + off);
+    off = align_up(off + (size_t)R * sizeof(EnsEntry));
+    e->items = (int4 *)(ws + off);
+    e->nitems = nitems;
+    EnsEntry *htab = new EnsEntry[R];
+    int4 *hitems = new int4[nitems > 0 ? nitems : 1];
+    int k = 0;
+    for (int r = 0; r < R && rc == LF_OK; ++r) {
+        lf_params q = ens_sub_params(&per[r], &per[0]);
+        rc = lf_create(&q, stream, ws + so[r], so[r + 1] - so[r], &e->sub[r]);
+        if (rc) break;
+        lf_ctx *c = e->sub[r];
+        EnsEntry &t = htab[r];
+        memset(&t, 0, sizeof t);
+        for (int b = 0; b < 2; ++b)
+            for (int j = 0; j < 4; ++j) t.buf[b][j] = c->buf[b][j];
+        t.part = c->part;
+        t.C = c->C;
+        t.Cw = c->C;
+        t.P = c->P;
+        t.S = c->S;
+        t.N = q.N;
+        t.zchunk = c->sh.zchunk;
+        t.ntx = (q.N + c->sh.tile_x - 1) / c->sh.tile_x;
+        t.nty = (q.N + c->sh.tile_y - 1) / c->sh.tile_y;
+        t.rows = c->sh.rows;
+        for (int j = 0; j < c->sh.rows; ++j) hitems[k++] = make_int4(r, j, j, 0);
+    }
+    delete[] so;
+    if (rc == LF_OK) {
+        hipError_t he = hipMemcpyAsync(e->tab, htab, (size_t)R * sizeof(EnsEntry), hipMemcpyHostToDevice, e->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(e->items, hitems, (size_t)nitems * sizeof(int4), hipMemcpyHostToDevice, e->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+        if (he != hipSuccess) rc = fail(LF_EHIP, "uploading the ensemble tables: %s", hipGetErrorString(he));
+    }
+    delete[] htab;
+    delete[] hitems;
+    if (rc) {
+        lf_ens_destroy(e);
+        return rc;
+    }
+    // persistent grid: as many blocks as fit on the device at once
+    const lf_params q0 = ens_sub_params(&per[0], &per[0]);
+    int res = resident_blocks(&q0, e->tile_x, e->tile_y);
+    e->grid = nitems < res ? nitems : res;
+    *out = e;
+    return LF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void ens_enqueue_step(lf_ens *e, int parity, hipStream_t st)
+{
+    launch_aupdate_ens(e->tab, e->R, st);
+    launch_sweep_ens(e->dtype, e->tile_x, e->tile_y, e->beta, e->tab, e->items, e->nitems, e->grid,
+                     parity, st);
+}
+
+int ens_capture(lf_ens *e, int nsteps, int start, hipGraphExec_t *exec)
+{
+    if (!e->cap) HIPCHK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+    int par = start;
+    for (int k = 0; k < nsteps; ++k, par ^= 1) ens_enqueue_step(e, par, e->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(e->cap, &g);
+    if (e1 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LF_EHIP, "kernel launch during capture: %s", hipGetErrorString(e1));
+    }
+    if (e2 != hipSuccess) return fail(LF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(LF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    return LF_OK;
+}
+
+int ens_check_inited(lf_ens *e)
+{
+    for (int r = 0; r < e->R; ++r)
+        if (!e->sub[r]->inited) return fail(LF_ESTATE, "realization %d is not initialised", r);
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_ens_size(lf_ens *e, int *R) {
+    if (!e || !R) return fail(LF_EINVAL, "NULL argument");
+    *R = e->R;
+    return LF_OK;
+}
+
+int lf_ens_init(lf_ens *e, int r, const void *f1, const void *f2, const void *v1, const void *v2,
+                int in_dtype, double a0, double ad0)
+{
+    if (!e) return fail(LF_EINVAL, "ensemble is NULL");
+    if (r < 0 || r >= e->R) return fail(LF_EINVAL, "realization %d out of range", r);
+    if (e->cur != 0) return fail(LF_ESTATE, "initialise every realization before stepping");
+    return lf_init(e->sub[r], f1, f2, v1, v2, in_dtype, a0, ad0);
+}
+
+int lf_ens_init_physical(lf_ens *e, int r, const void *f1, const void *f2, const void *u1,
+                         const void *u2, int in_dtype, double a0, double *ad0_out)
+{
+    if (!e) return fail(LF_EINVAL, "ensemble is NULL");
+    if (r < 0 || r >= e->R) return fail(LF_EINVAL, "realization %d out of range", r);
+    if (e->cur != 0) return fail(LF_ESTATE, "initialise every realization before stepping");
+    return lf_init_physical(e->sub[r], f1, f2, u1, u2, in_dtype, a0, ad0_out);
+}
+
+int lf_ens_step(lf_ens *e, int64_t n)
+{
+    if (!e) return fail(LF_EINVAL, "ensemble is NULL");
+    if (n < 0) return fail(LF_EINVAL, "n=%lld < 0", (long long)n);
+    int rc = ens_check_inited(e);
+    if (rc) return rc;
+    if (n == 0) return LF_OK;
+    if (n >= 2 && !e->g2 && (rc = ens_capture(e, 2, 0, &e->g2))) return rc;
+    if ((rc = ensure_events(&e->ev0, &e->ev1))) return rc;
+    HIPCHK(hipEventRecord(e->ev0, e->stream));
+    while (n > 0) {
+        if (n >= 2 && e->cur == 0) {
+            HIPCHK(hipGraphLaunch(e->g2, e->stream));
+            n -= 2;
+        } else {
+            if (!e->g1[e->cur] && (rc = ens_capture(e, 1, e->cur, &e->g1[e->cur]))) return rc;
+            HIPCHK(hipGraphLaunch(e->g1[e->cur], e->stream));
+            e->cur ^= 1;
+            --n;
+        }
+    }
+    HIPCHK(hipEventRecord(e->ev1, e->stream));
+    e->timed = 1;
+    for (int r = 0; r < e->R; ++r) e->sub[r]->cur = e->cur;
+    return LF_OK;
+}
+
+int lf_ens_last_step_ms(lf_ens *e, double *ms)
+{
+    if (!e || !ms) return fail(LF_EINVAL, "NULL argument");
+    *ms = 0.0;
+    if (!e->timed) return LF_OK;
+    HIPCHK(hipEventSynchronize(e->ev1));
+    float f = 0.0f;
+    HIPCHK(hipEventElapsedTime(&f, e->ev0, e->ev1));
+    *ms = f;
+    return LF_OK;
+}
+
+int lf_ens_energies(lf_ens *e, lf_report *out)
+{
+    if (!e || !out) return fail(LF_EINVAL, "NULL argument");
+    int worst = LF_OK;
+    for (int r = 0; r < e->R; ++r) {
+        int rc = lf_energies(e->sub[r], &out[r]);
+        if (rc == LF_ENONFINITE) worst = rc;
+        else if (rc) return rc;
+    }
+    if (worst) return fail(worst, "non-finite value in at least one realization");
+    return LF_OK;
+}
+
+int lf_ens_get_fields(lf_ens *e, int r, void *f1, void *f2, void *v1, void *v2, int out_dtype,
+                      int synchronized)
+{
+    if (!e) return fail(LF_EINVAL, "ensemble is NULL");
+    if (r < 0 || r >= e->R) return fail(LF_EINVAL, "realization %d out of range", r);
+    return lf_get_fields(e->sub[r], f1, f2, v1, v2, out_dtype, synchronized);
 }
 
 }  // extern "C"

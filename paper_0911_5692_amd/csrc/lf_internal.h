@@ -56,7 +56,18 @@ struct CoefPair {
     double g1n, g2n;    // background at k+3/2 (FP64), for the reduction of f_new
 };
 
-// Launch helpers (lf_kernels.hip).  All enqueue on `st`.
+// One realization of an ensemble, as the batched kernels see it.
+struct EnsEntry {
+    void *buf[2][4];        // ping/pong deviation arrays d1, d2, e1, e2
+    double *part;           // partial-sum rows of this realization
+    const CoefPair *C;      // its per-step coefficients
+    const DevParams *P;
+    DevScalars *S;
+    CoefPair *Cw;           // same as C, writable (scale-factor kernel)
+    int N, zchunk, ntx, nty, rows, pad;
+};
+
+// Launch helpers (lf_kernels.hip, lf_sweep.hip).  All enqueue on `st`.
 void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
                           const void *v2, int N, int beta, double *part, int nblk, hipStream_t st);
 void launch_init_scalars(const double *part, int nblk, const DevParams *P, DevScalars *S,
@@ -68,8 +79,18 @@ void launch_reduce(int dtype, const void *d1, const void *d2, int N, const doubl
                    int beta, double *part, int nblk, hipStream_t st);
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S,
                     CoefPair *C, hipStream_t st);
-void launch_sweep_plain(int dtype, const void *const in[4], void *const out[4], int N,
+void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st);
+void launch_sweep_ens(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
+                      const int4 *items, int nitems, int grid, int parity, hipStream_t st);
+void launch_sweep_plain(int dtype, int beta, const void *const in[4], void *const out[4], int N,
                         const CoefPair *C, hipStream_t st);
+void launch_sweep_lds(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+                      void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
+                      hipStream_t st);
+int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk);
+// Resident blocks per CU of the LDS sweep instantiation (0 if unknown, e.g.
+// no device).
+int sweep_lds_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);
 void launch_energy(int dtype, const void *const st4[4], int N, const DevParams *P,
                    const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st);
 void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],

@@ -244,9 +244,8 @@ __device__ inline double binom_d(int n, int k)
 //      coefficient vanishes, written in the cancellation-free form)
 //   a'_{k+1/2} = (a'_k + a'_{k+1})/2, a''_{k+1/2} = (a'_{k+1} - a'_k)/dt,
 //   a_{k+3/2} = a_{k+1/2} + dt a'_{k+1}.
-__global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, int nblk,
-                                                            const DevParams *__restrict__ P,
-                                                            DevScalars *S, CoefPair *C)
+__device__ void aupdate_block(const double *part, int nblk, const DevParams *__restrict__ P,
+                              DevScalars *S, CoefPair *C)
 {
     double t[kNPart];
     stage2_sum<kNPart>(part, nblk, t);
@@ -301,6 +300,20 @@ __global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, 
     S->bg_f[0] = g1n; S->bg_f[1] = g2n;
     S->bg_v[0] = vb1; S->bg_v[1] = vb2;
     S->step += 1;
+}
+
+__global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, int nblk,
+                                                            const DevParams *__restrict__ P,
+                                                            DevScalars *S, CoefPair *C)
+{
+    aupdate_block(part, nblk, P, S, C);
+}
+
+// Ensemble: block r updates realization r.
+__global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *tab)
+{
+    const EnsEntry &e = tab[blockIdx.x];
+    aupdate_block(e.part, e.rows, e.P, e.S, e.Cw);
 }
 
 // ---------------------------------------------------------------- energies
@@ -463,6 +476,11 @@ void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars
                     hipStream_t st)
 {
     hipLaunchKernelGGL(k_aupdate, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, C);
+}
+
+void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_aupdate_ens, dim3(R), dim3(kStage2Threads), 0, st, tab);
 }
 
 void launch_energy(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,

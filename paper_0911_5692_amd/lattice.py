@@ -42,13 +42,14 @@ class Lattice:
     def __init__(self, N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float,
                  s: float, kappa2: float, dtype: torch.dtype = torch.float32,
                  device: str | torch.device = "cuda", tile_y: int = 0, zchunk: int = 0,
-                 stream: torch.cuda.Stream | None = None):
+                 tile_x: int = 0, stream: torch.cuda.Stream | None = None):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.N, self.dtype = int(N), dtype
         self.device = torch.device(device)
         self.params = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1),
-                             float(G), float(r), float(s), float(kappa2), int(tile_y), int(zchunk))
+                             float(G), float(r), float(s), float(kappa2), int(tile_y), int(zchunk),
+                             int(tile_x), 0)
         size = ctypes.c_size_t()
         check(lib().lf_workspace_bytes(ctypes.byref(self.params), ctypes.byref(size)))
         self.ws_bytes = size.value
@@ -144,3 +145,78 @@ class Lattice:
     def set_state(self, arrays, scalars: Scalars) -> None:
         ptrs = [_dev_ptr(t, self.dtype, self.shape) for t in arrays]
         check(lib().lf_set_state(self._ctx, *ptrs, ctypes.byref(scalars)))
+
+
+def _report_dict(rep: Report) -> dict:
+    return dict(step=rep.step, a=rep.a, ad=rep.ad, hubble=rep.hubble, K1=rep.K[0], K2=rep.K[1],
+                G1=rep.Gr[0], G2=rep.Gr[1], P=rep.P, rho=rep.rho, R=rep.R, status=rep.status)
+
+
+class Ensemble:
+    """R independent lattices stepped together by liblf's batched kernels.
+
+    members: list of dicts with the Lattice keyword arguments N, L, dt, beta,
+    c1, G, r, s, kappa2 (dtype and beta common to all)."""
+
+    def __init__(self, members, dtype: torch.dtype = torch.float32, device="cuda", tile_x: int = 0,
+                 tile_y: int = 0, zchunks=None, stream: torch.cuda.Stream | None = None):
+        self.R = len(members)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        arr = (Params * self.R)()
+        for i, m in enumerate(members):
+            zc = int(zchunks[i]) if zchunks is not None else 0
+            arr[i] = Params(int(m["N"]), _DT[dtype], float(m["L"]), float(m["dt"]), int(m["beta"]), 0,
+                            float(m["c1"]), float(m["G"]), float(m["r"]), float(m["s"]),
+                            float(m["kappa2"]), int(tile_y), zc, int(tile_x), 0)
+        self.params = arr
+        self.Ns = [int(m["N"]) for m in members]
+        size = ctypes.c_size_t()
+        check(lib().lf_ens_workspace_bytes(self.R, arr, ctypes.byref(size)))
+        self.ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().lf_ens_create(self.R, arr, ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.c_void_p(self.ws.data_ptr()), size.value, ctypes.byref(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().lf_ens_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_physical(self, r: int, f1, f2, u1, u2, a0: float = 1.0) -> float:
+        N = self.Ns[r]
+        ts = [_aligned(t) for t in (f1, f2, u1, u2)]
+        dt = ts[0].dtype
+        ptrs = [_dev_ptr(t, dt, (N, N, N)) for t in ts]
+        ad0 = ctypes.c_double()
+        check(lib().lf_ens_init_physical(self._h, int(r), *ptrs, _DT[dt], float(a0), ctypes.byref(ad0)))
+        return ad0.value
+
+    def step(self, n: int = 1) -> None:
+        check(lib().lf_ens_step(self._h, int(n)))
+
+    def last_step_ms(self) -> float:
+        ms = ctypes.c_double()
+        check(lib().lf_ens_last_step_ms(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def energies(self):
+        reps = (Report * self.R)()
+        check(lib().lf_ens_energies(self._h, reps))
+        return [_report_dict(reps[i]) for i in range(self.R)]
+
+    def fields(self, r: int, synchronized: bool = False, dtype: torch.dtype = torch.float64):
+        N = self.Ns[r]
+        out = [torch.empty((N, N, N), dtype=dtype, device=self.device) for _ in range(4)]
+        ptrs = [_dev_ptr(t, dtype, (N, N, N)) for t in out]
+        check(lib().lf_ens_get_fields(self._h, int(r), *ptrs, _DT[dtype], 1 if synchronized else 0))
+        self.stream.synchronize()
+        return tuple(out)
