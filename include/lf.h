@@ -190,6 +190,30 @@ int lf_set_coupling(lf_ctx *ctx, double G);
  * enqueued, in ms (blocking; 0 if none). */
 int lf_last_step_ms(lf_ctx *ctx, double *ms);
 
+/* ---- adjoint (reverse-mode gradient) ------------------------------------ */
+
+/* Loss E = w[0] K_1 + w[1] K_2 + w[2] Gr_1 + w[3] Gr_2 of the synchronised
+ * energies after n steps (e.g. w = {0, 1, 0, 1}: the chi kinetic plus gradient
+ * energy).  Its gradient with respect to G and to the synchronised initial
+ * state (f1, f2, v1, v2 at tau = 0, a_0, a'_0) is the transpose of the
+ * leapfrog map's Jacobian applied in reverse step order (the paper gives the
+ * forward map, Sec. II.B; the adjoint is this library's).  Memory: states at
+ * steps 0, K, 2K, ... are checkpointed in a caller-owned workspace of
+ * lf_adj_workspace_bytes bytes; the backward pass recomputes each K-step
+ * segment from its checkpoint, keeps its K states in the same workspace and
+ * runs the reverse steps on the exact forward states.  Cotangents are FP64. */
+int lf_adj_workspace_bytes(const lf_params *p, int64_t n, int K, size_t *out_bytes);
+/* Context just initialised (no step yet).  Runs n steps (the context then
+ * holds step n) and returns the loss.  Blocking.  adj_ws must stay alive
+ * until lf_adj_backward. */
+int lf_adj_forward(lf_ctx *ctx, int64_t n, int K, const double *w, void *adj_ws, size_t ws_bytes,
+                   double *loss);
+/* dL/dE = dL.  Writes dL/dG, dL/da0, dL/da'0 and the N^3 FP64 device arrays
+ * dL/df1(0), dL/df2(0), dL/dv1(0), dL/dv2(0).  Blocking.  Afterwards the
+ * context holds an intermediate state: initialise it again before reuse. */
+int lf_adj_backward(lf_ctx *ctx, double dL, double *dL_dG, void *g_f1, void *g_f2, void *g_v1,
+                    void *g_v2, double *dL_da0, double *dL_dad0);
+
 /* ---- ensemble of independent lattices --------------------------------- */
 
 /* R realizations evolved together: per_real[r] gives each one's lattice and

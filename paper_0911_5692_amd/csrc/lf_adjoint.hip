@@ -1,0 +1,373 @@
+// Reverse-mode (adjoint) kernels of the leapfrog map, gfx950.
+//
+// The forward step X_k -> X_{k+1} (Sainio, arXiv:0911.5692, eq. evo applied
+// to eq. scalar-evo and eq. scale; X = f(k+1/2), v(k), a_{k+1/2}, a'_k) is
+// differentiated by hand; its transpose is applied here step by step in
+// reverse order.  Per reverse step:
+//   pass A  (k_adj_reduce): volume sums of the incoming cotangent against the
+//           stored fields (the global a'' coupling) and of the fields themselves;
+//   scalar  (k_adj_scalar): the chain through a'', the time-centred a' update,
+//           F_a and the a-powers of V_pr, in FP64, one thread;
+//   pass B  (k_adj_fields): the field cotangents: the 7-point Laplacian of
+//           mu = lambda_v' + dt lambda_f' (the stencil is symmetric), the local
+//           2x2 Hessian of V_pr, and the rank-one terms from Sg and SV.
+// Cotangent arrays are FP64 whatever the state precision; stored states are
+// deviations from the FP64 background and are turned back into full fields
+// f = f_bar + d in FP64 on the fly.
+#include "lf_internal.h"
+
+#include <math.h>
+
+namespace lf {
+
+namespace {
+
+template <int NV>
+__device__ inline void bsum(double (&v)[NV], double *out)
+{
+    __shared__ double sm[NV][4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sm[i][wave] = v[i];
+    }
+    __syncthreads();
+    if (t < NV) out[t] = ((sm[t][0] + sm[t][1]) + sm[t][2]) + sm[t][3];
+}
+
+template <int NV>
+__device__ inline void stage2(const double *part, int nblk, double (&tot)[NV])
+{
+    __shared__ double res[NV];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int j = threadIdx.x; j < nblk; j += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)j * NV + i];
+    }
+    bsum<NV>(acc, res);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = res[i];
+}
+
+__device__ inline double ipw(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+struct Nbr {
+    int64_t i, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ inline Nbr nbr_of(int64_t i, int N)
+{
+    const int64_t NN = (int64_t)N * N;
+    const int x = (int)(i % N);
+    const int64_t t = i / N;
+    const int y = (int)(t % N), z = (int)(t / N);
+    Nbr n;
+    n.i = i;
+    n.xm = (x == 0) ? i + (N - 1) : i - 1;
+    n.xp = (x == N - 1) ? i - (N - 1) : i + 1;
+    n.ym = (y == 0) ? i + (int64_t)(N - 1) * N : i - N;
+    n.yp = (y == N - 1) ? i - (int64_t)(N - 1) * N : i + N;
+    n.zm = (z == 0) ? i + (int64_t)(N - 1) * NN : i - NN;
+    n.zp = (z == N - 1) ? i - (int64_t)(N - 1) * NN : i + NN;
+    return n;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ loss seed
+
+// Cotangent of E = sum_i wK_i K_i + wG_i G_i at the synchronised time of
+// the state (d, e; background and scale factor in S), written to lam[0..3]
+// (lambda_f1, lambda_f2, lambda_v1, lambda_v2), plus the per-block sums the
+// scalar part needs: sum q1^2, sum q2^2, sum |d+ fs1|^2, sum |d+ fs2|^2 (raw),
+// sum_i wK_i q_i fs_i.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_seed(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                  const T *__restrict__ e1, const T *__restrict__ e2,
+                                                  int N, const DevParams *__restrict__ P,
+                                                  const DevScalars *__restrict__ S, const double *__restrict__ w,
+                                                  double *lf1, double *lf2, double *lv1, double *lv2,
+                                                  double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const double h = 0.5 * P->dt, r = P->r, s = P->s, inv_dx2 = 1.0 / (P->dx * P->dx);
+    const double a = S->a_half - h * S->ad, hub = S->ad / a;
+    const double gfac = 0.5 * pow(a, -2.0 * s - 2.0);
+    const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
+    const double wK1 = w[0], wK2 = w[1], wG1 = w[2], wG2 = w[3];
+    const double n3 = (double)N3;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Nbr n = nbr_of(i, N);
+        auto sy1 = [&](int64_t j) { return (double)d1[j] - h * (double)e1[j]; };
+        auto sy2 = [&](int64_t j) { return (double)d2[j] - h * (double)e2[j]; };
+        const double c1v = sy1(i), c2v = sy2(i);
+        const double fs1 = gs1 + c1v, fs2 = gs2 + c2v;
+        const double q1 = (S->bg_v[0] + (double)e1[i]) - r * hub * fs1;
+        const double q2 = (S->bg_v[1] + (double)e2[i]) - r * hub * fs2;
+        const double lap1 = (((sy1(n.xm) + sy1(n.xp)) + (sy1(n.ym) + sy1(n.yp))) + (sy1(n.zm) + sy1(n.zp)) - 6.0 * c1v) * inv_dx2;
+        const double lap2 = (((sy2(n.xm) + sy2(n.xp)) + (sy2(n.ym) + sy2(n.yp))) + (sy2(n.zm) + sy2(n.zp)) - 6.0 * c2v) * inv_dx2;
+        const double dq1 = wK1 * q1 / n3, dq2 = wK2 * q2 / n3;
+        const double dfs1 = -r * hub * dq1 - 2.0 * wG1 * gfac * lap1 / n3;
+        const double dfs2 = -r * hub * dq2 - 2.0 * wG2 * gfac * lap2 / n3;
+        lf1[i] = dfs1;
+        lf2[i] = dfs2;
+        lv1[i] = dq1 - h * dfs1;
+        lv2[i] = dq2 - h * dfs2;
+        acc[0] += q1 * q1;
+        acc[1] += q2 * q2;
+        double t0 = sy1(n.xp) - c1v, t1 = sy1(n.yp) - c1v, t2 = sy1(n.zp) - c1v;
+        acc[2] += t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = sy2(n.xp) - c2v; t1 = sy2(n.yp) - c2v; t2 = sy2(n.zp) - c2v;
+        acc[3] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[4] += wK1 * q1 * fs1 + wK2 * q2 * fs2;
+    }
+    bsum<5>(acc, part + (size_t)blockIdx.x * 5);
+}
+
+// Scalar part of the seed and the loss value.  A: [la, lw, gG, E, ...].
+__global__ void __launch_bounds__(256) k_adj_seed_scalar(const double *part, int nblk,
+                                                         const DevParams *__restrict__ P,
+                                                         const DevScalars *__restrict__ S,
+                                                         const double *__restrict__ w, double *A)
+{
+    double t[5];
+    stage2<5>(part, nblk, t);
+    if (threadIdx.x != 0) return;
+    const double h = 0.5 * P->dt, r = P->r, s = P->s, n3 = P->N3;
+    const double a = S->a_half - h * S->ad, ad = S->ad;
+    const double gfac = 0.5 * pow(a, -2.0 * s - 2.0) / (P->dx * P->dx);
+    const double K1 = 0.5 * t[0] / n3, K2 = 0.5 * t[1] / n3;
+    const double G1 = gfac * t[2] / n3, G2 = gfac * t[3] / n3;
+    const double E = w[0] * K1 + w[1] * K2 + w[2] * G1 + w[3] * G2;
+    const double dhub = -r * t[4] / n3;
+    const double dEda = dhub * (-ad / (a * a)) + (w[2] * G1 + w[3] * G2) * (-2.0 * s - 2.0) / a;
+    const double dEdad = dhub / a;
+    A[0] = dEda;              // lambda of a_{n+1/2}
+    A[1] = dEdad - h * dEda;  // lambda of a'_n
+    A[2] = 0.0;               // dE/dG accumulator
+    A[3] = E;
+}
+
+// ------------------------------------------------------------ reverse step
+
+// Pass A: sums over the stored fields f = f_bar + d at k+1/2 and
+// mu = lambda_v' + dt lambda_f' (cotangent of v(k+1)):
+//  0: sum mu_i S6(f_i)   1: sum mu_i f_i   2: sum mu1 f1 f2^2 + mu2 f1^2 f2
+//  3: sum mu1 f1^(beta-1)   4: sum f1^beta   5: sum f1^2 f2^2   6: sum |d+ f_i|^2
+// (S6: raw 6-neighbour sum minus 6 f; no 1/dx^2)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_reduce(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                    int N, int beta, const DevScalars *__restrict__ tape,
+                                                    const double *__restrict__ lf1, const double *__restrict__ lf2,
+                                                    const double *__restrict__ lv1, const double *__restrict__ lv2,
+                                                    double dt, double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const double g1 = tape->bg_f[0], g2 = tape->bg_f[1];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Nbr n = nbr_of(i, N);
+        const double a1 = (double)d1[i], a2 = (double)d2[i];
+        const double f1 = g1 + a1, f2 = g2 + a2;
+        const double s1 = ((((double)d1[n.xm] + (double)d1[n.xp]) + ((double)d1[n.ym] + (double)d1[n.yp]))
+                           + ((double)d1[n.zm] + (double)d1[n.zp])) - 6.0 * a1;
+        const double s2 = ((((double)d2[n.xm] + (double)d2[n.xp]) + ((double)d2[n.ym] + (double)d2[n.yp]))
+                           + ((double)d2[n.zm] + (double)d2[n.zp])) - 6.0 * a2;
+        const double mu1 = lv1[i] + dt * lf1[i], mu2 = lv2[i] + dt * lf2[i];
+        acc[0] += mu1 * s1 + mu2 * s2;
+        acc[1] += mu1 * f1 + mu2 * f2;
+        acc[2] += mu1 * f1 * f2 * f2 + mu2 * f1 * f1 * f2;
+        acc[3] += mu1 * ipw(f1, beta - 1);
+        acc[4] += ipw(f1, beta);
+        acc[5] += f1 * f1 * f2 * f2;
+        double t0 = (double)d1[n.xp] - a1, t1 = (double)d1[n.yp] - a1, t2 = (double)d1[n.zp] - a1;
+        double gsum = t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = (double)d2[n.xp] - a2; t1 = (double)d2[n.yp] - a2; t2 = (double)d2[n.zp] - a2;
+        acc[6] += gsum + t0 * t0 + t1 * t1 + t2 * t2;
+    }
+    bsum<7>(acc, part + (size_t)blockIdx.x * 7);
+}
+
+// Scalar chain of one reverse step.  A: [la, lw, gG, E]; writes the field
+// coefficients to cf: [dt a^(-2s-2)/dx^2, dt bcoef, c1 a^p1, G a^p2, cSg, cSV, dt].
+__global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk,
+                                                    const DevParams *__restrict__ P,
+                                                    const DevScalars *__restrict__ tape, double *A,
+                                                    double *cf)
+{
+    double R[7];
+    stage2<7>(part, nblk, R);
+    if (threadIdx.x != 0) return;
+    const double n3 = P->N3, dx = P->dx, dt = P->dt, r = P->r, s = P->s, c1 = P->c1, G = P->G;
+    const int beta = P->beta;
+    const double a = tape->a_half, w = tape->ad;
+    const double p1 = P->p1, p2 = P->p2;
+    const double ap1 = pow(a, p1), ap2 = pow(a, p2);
+    const double dap1 = p1 * pow(a, p1 - 1.0), dap2 = p2 * pow(a, p2 - 1.0);
+    // forward scalars of this step
+    const double Sg = R[6] / (dx * dx * n3);
+    const double SV = (c1 * ap1 * R[4] / (double)beta + 0.5 * G * ap2 * R[5]) / n3;
+    const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
+    const double c = (-s - 2.0) * dt / (4.0 * a);
+    const double disc = 1.0 - 8.0 * c * w - 4.0 * c * dt * Fa;
+    const double u = 2.0 * (c * w * w + w + dt * Fa) / ((1.0 - 2.0 * c * w) + sqrt(disc));
+    const double adh = 0.5 * (w + u), add = (u - w) / dt;
+    const double alpha = pow(a, -2.0 * s - 2.0);
+    const double rr = r * (s - r + 2.0);
+    const double bc = rr * (adh / a) * (adh / a) + r * add / a;
+    // kick sensitivities
+    const double galpha = dt * R[0] / (dx * dx);
+    const double gbeta = dt * R[1];
+    const double gGk = -dt * ap2 * R[2];
+    const double gak = -dt * (c1 * dap1 * R[3] + G * dap2 * R[2]);
+    const double sdVda = c1 * dap1 * R[4] / (double)beta + 0.5 * G * dap2 * R[5];
+    const double sdVdG = 0.5 * ap2 * R[5];
+    const double la = A[0], lw = A[1];
+    double ga = la + gak;
+    ga += galpha * (-2.0 * s - 2.0) * pow(a, -2.0 * s - 3.0);
+    const double g_adh = gbeta * 2.0 * rr * adh / (a * a);
+    const double g_add = gbeta * r / a;
+    ga += gbeta * (-2.0 * rr * adh * adh / (a * a * a) - r * add / (a * a));
+    const double g_u = lw + dt * la + 0.5 * g_adh + g_add / dt;
+    double g_w = 0.5 * g_adh - g_add / dt;
+    const double q = dt * (-s - 2.0) * (w + u) / (2.0 * a);
+    const double hu = 1.0 - q;
+    g_w += g_u * (1.0 + q) / hu;
+    ga += g_u * (-(dt * (-s - 2.0) * (w + u) * (w + u) / (4.0 * a * a)) / hu);
+    const double gF = g_u * dt / hu;
+    const double e1 = -2.0 * s - 2.0 * r - 1.0;
+    const double gSg = gF * P->kappa2 * pow(a, e1) / 3.0;
+    const double gSV = gF * P->kappa2 * pow(a, e1 + 2.0 * s + 2.0);
+    ga += gF * P->kappa2 * (e1 * pow(a, e1 - 1.0) * Sg / 3.0 + (e1 + 2.0 * s + 2.0) * pow(a, e1 + 2.0 * s + 1.0) * SV);
+    ga += gSV * sdVda / n3;
+    A[0] = ga;
+    A[1] = g_w;
+    A[2] += gGk + gSV * sdVdG / n3;
+    cf[0] = dt * alpha / (dx * dx);
+    cf[1] = dt * bc;
+    cf[2] = c1 * ap1;
+    cf[3] = G * ap2;
+    cf[4] = -2.0 * gSg / (n3 * dx * dx);  // multiplies the raw 6-neighbour sum of f
+    cf[5] = gSV / n3;
+    cf[6] = dt;
+}
+
+// Pass B: field cotangents of X_k from those of X_{k+1} (in -> out).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                    int N, int beta, const DevScalars *__restrict__ tape,
+                                                    const double *__restrict__ cf,
+                                                    const double *__restrict__ lf1, const double *__restrict__ lf2,
+                                                    const double *__restrict__ lv1, const double *__restrict__ lv2,
+                                                    double *of1, double *of2, double *ov1, double *ov2)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const double g1 = tape->bg_f[0], g2 = tape->bg_f[1];
+    const double cl = cf[0], cb = cf[1], c1a = cf[2], Ga = cf[3], cSg = cf[4], cSV = cf[5], dt = cf[6];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Nbr n = nbr_of(i, N);
+        auto mu1 = [&](int64_t j) { return lv1[j] + dt * lf1[j]; };
+        auto mu2 = [&](int64_t j) { return lv2[j] + dt * lf2[j]; };
+        const double m1 = mu1(i), m2 = mu2(i);
+        const double lm1 = (((mu1(n.xm) + mu1(n.xp)) + (mu1(n.ym) + mu1(n.yp))) + (mu1(n.zm) + mu1(n.zp))) - 6.0 * m1;
+        const double lm2 = (((mu2(n.xm) + mu2(n.xp)) + (mu2(n.ym) + mu2(n.yp))) + (mu2(n.zm) + mu2(n.zp))) - 6.0 * m2;
+        const double a1 = (double)d1[i], a2 = (double)d2[i];
+        const double s1 = ((((double)d1[n.xm] + (double)d1[n.xp]) + ((double)d1[n.ym] + (double)d1[n.yp]))
+                           + ((double)d1[n.zm] + (double)d1[n.zp])) - 6.0 * a1;
+        const double s2 = ((((double)d2[n.xm] + (double)d2[n.xp]) + ((double)d2[n.ym] + (double)d2[n.yp]))
+                           + ((double)d2[n.zm] + (double)d2[n.zp])) - 6.0 * a2;
+        const double f1 = g1 + a1, f2 = g2 + a2;
+        const double h11 = c1a * (double)(beta - 1) * ipw(f1, beta - 2) + Ga * f2 * f2;
+        const double h12 = 2.0 * Ga * f1 * f2;
+        const double h22 = Ga * f1 * f1;
+        const double dv1 = c1a * ipw(f1, beta - 1) + Ga * f1 * f2 * f2;
+        const double dv2 = Ga * f1 * f1 * f2;
+        of1[i] = lf1[i] + cl * lm1 + cb * m1 - dt * (h11 * m1 + h12 * m2) + cSg * s1 + cSV * dv1;
+        of2[i] = lf2[i] + cl * lm2 + cb * m2 - dt * (h12 * m1 + h22 * m2) + cSg * s2 + cSV * dv2;
+        ov1[i] = m1;
+        ov2[i] = m2;
+    }
+}
+
+// Transpose of the desynchronisation f(1/2) = f(0) + dt/2 v(0) (in place on
+// the v cotangents) and of a_{1/2} = a0 + dt/2 a'0 (A[1] += dt/2 A[0]).
+__global__ void __launch_bounds__(256) k_adj_desync(int64_t N3, double h, const double *lf1,
+                                                    const double *lf2, double *lv1, double *lv2, double *A)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        lv1[i] += h * lf1[i];
+        lv2[i] += h * lf2[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) A[1] += h * A[0];
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_adj_seed(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
+                     const double *w, double *const lam[4], double *part, int nblk, double *A,
+                     hipStream_t st)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_adj_seed<float>, dim3(nblk), dim3(256), 0, st, (const float *)s4[0],
+                           (const float *)s4[1], (const float *)s4[2], (const float *)s4[3], N, P, S, w,
+                           lam[0], lam[1], lam[2], lam[3], part);
+    else
+        hipLaunchKernelGGL(k_adj_seed<double>, dim3(nblk), dim3(256), 0, st, (const double *)s4[0],
+                           (const double *)s4[1], (const double *)s4[2], (const double *)s4[3], N, P, S, w,
+                           lam[0], lam[1], lam[2], lam[3], part);
+    hipLaunchKernelGGL(k_adj_seed_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, S, w, A);
+}
+
+void launch_adj_step(int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
+                     const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
+                     double *part, int nblk, double *A, double *cf, hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    int64_t g = (N3 + 255) / 256;
+    const int gridB = (int)(g > 65536 ? 65536 : g);
+    if (dtype == 0) {
+        hipLaunchKernelGGL(k_adj_reduce<float>, dim3(nblk), dim3(256), 0, st, (const float *)d1,
+                           (const float *)d2, N, beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
+        hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
+        hipLaunchKernelGGL(k_adj_fields<float>, dim3(gridB), dim3(256), 0, st, (const float *)d1,
+                           (const float *)d2, N, beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0],
+                           lout[1], lout[2], lout[3]);
+    } else {
+        hipLaunchKernelGGL(k_adj_reduce<double>, dim3(nblk), dim3(256), 0, st, (const double *)d1,
+                           (const double *)d2, N, beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
+        hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
+        hipLaunchKernelGGL(k_adj_fields<double>, dim3(gridB), dim3(256), 0, st, (const double *)d1,
+                           (const double *)d2, N, beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0],
+                           lout[1], lout[2], lout[3]);
+    }
+}
+
+void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    int64_t g = (N3 + 255) / 256;
+    hipLaunchKernelGGL(k_adj_desync, dim3((int)(g > 65536 ? 65536 : g)), dim3(256), 0, st, N3, 0.5 * dt,
+                       lam[0], lam[1], lam[2], lam[3], A);
+}
+
+}  // namespace lf

@@ -175,6 +175,12 @@ struct lf_ctx {
     int K;
     hipEvent_t ev0, ev1;
     int timed;
+    int64_t hstep;  // steps since lf_init / lf_set_state, as enqueued by the host
+    // adjoint bookkeeping (lf_adj_forward / lf_adj_backward)
+    char *adj_ws;
+    int64_t adj_n;
+    int adj_K, adj_ready;
+    double adj_w[4];
 };
 
 namespace {
@@ -349,6 +355,8 @@ static int init_common(lf_ctx *c, const void *f1, const void *f2, const void *v1
     c->cur = 0;
     c->inited = 1;
     c->timed = 0;
+    c->hstep = 0;
+    c->adj_ready = 0;
     return LF_OK;
 }
 
@@ -378,6 +386,7 @@ int lf_step(lf_ctx *c, int64_t n)
     if (n < 0) return fail(LF_EINVAL, "n=%lld < 0", (long long)n);
     if (!c->inited) return fail(LF_ESTATE, "lf_step before lf_init");
     if (n == 0) return LF_OK;
+    const int64_t n0 = n;
     int rc;
     if (n >= c->K && !c->gK[c->cur] && (rc = capture(c, c->K, c->cur, &c->gK[c->cur]))) return rc;
     if ((rc = ensure_events(&c->ev0, &c->ev1))) return rc;
@@ -394,6 +403,7 @@ int lf_step(lf_ctx *c, int64_t n)
     }
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = 1;
+    c->hstep += n0;
     return LF_OK;
 }
 
@@ -513,6 +523,8 @@ int lf_set_state(lf_ctx *c, const void *d1, const void *d2, const void *e1, cons
     HIPCHK(hipStreamSynchronize(c->stream));
     c->cur = 0;
     c->inited = 1;
+    c->hstep = s->step;
+    c->adj_ready = 0;
     return LF_OK;
 }
 
@@ -548,10 +560,173 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
         }
         if (e != hipSuccess) rc = fail(LF_EHIP, "timing step: %s", hipGetErrorString(e));
         c->cur ^= 1;
+        c->hstep += 1;
     }
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
     if (rc) return rc;
     for (int j = 0; j < n_out; ++j) ms[j] = (j < 3) ? acc[j] / (double)n : 0.0;
+    return LF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- adjoint
+
+namespace {
+
+struct AdjLayout {
+    int64_t nck;            // checkpoint slots (state at steps 0, K, 2K, ...)
+    size_t slot_bytes;      // one checkpoint: 4 arrays + scalars + pending sums
+    size_t arr_bytes;       // one lattice array of the context dtype
+    size_t ck, seg, tape, lam, part, A, cf, w, total;
+};
+
+AdjLayout adj_layout(const lf_params *p, int64_t n, int K)
+{
+    AdjLayout L{};
+    const size_t n3 = (size_t)p->N * p->N * p->N;
+    L.arr_bytes = align_up(n3 * esize(p->dtype));
+    L.nck = (n + K - 1) / K;
+    L.slot_bytes = 4 * L.arr_bytes + align_up(sizeof(DevScalars)) + align_up(8 * sizeof(double));
+    size_t off = 0;
+    L.ck = off; off += (size_t)L.nck * L.slot_bytes;
+    L.seg = off; off += (size_t)K * 4 * L.arr_bytes;
+    L.tape = off; off = align_up(off + (size_t)K * sizeof(DevScalars));
+    L.lam = off; off += 8 * align_up(n3 * sizeof(double));
+    L.part = off; off = align_up(off + (size_t)kRedBlocks * kNAdjPart * sizeof(double));
+    L.A = off; off = align_up(off + 8 * sizeof(double));
+    L.cf = off; off = align_up(off + 8 * sizeof(double));
+    L.w = off; off = align_up(off + 8 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int save_slot(lf_ctx *c, char *slot, const AdjLayout &L)
+{
+    const size_t bytes = (size_t)c->p.N * c->p.N * c->p.N * esize(c->p.dtype);
+    for (int j = 0; j < 4; ++j)
+        HIPCHK(hipMemcpyAsync(slot + j * L.arr_bytes, c->buf[c->cur][j], bytes, hipMemcpyDeviceToDevice, c->stream));
+    char *sc = slot + 4 * L.arr_bytes;
+    HIPCHK(hipMemcpyAsync(sc, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+    launch_sum_partials(c->part, c->sh.rows, kNPart, (double *)(sc + align_up(sizeof(DevScalars))), c->stream);
+    HIPCHK(hipGetLastError());
+    return LF_OK;
+}
+
+int restore_slot(lf_ctx *c, const char *slot, const AdjLayout &L)
+{
+    const size_t bytes = (size_t)c->p.N * c->p.N * c->p.N * esize(c->p.dtype);
+    for (int j = 0; j < 4; ++j)
+        HIPCHK(hipMemcpyAsync(c->buf[0][j], slot + j * L.arr_bytes, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const char *sc = slot + 4 * L.arr_bytes;
+    HIPCHK(hipMemcpyAsync(c->S, sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+    launch_set_pending(c->part, c->sh.rows, (const double *)(sc + align_up(sizeof(DevScalars))), c->stream);
+    HIPCHK(hipGetLastError());
+    c->cur = 0;
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_adj_workspace_bytes(const lf_params *p, int64_t n, int K, size_t *out_bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (n < 1 || K < 1) return fail(LF_EINVAL, "n and K must be >= 1");
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    *out_bytes = adj_layout(p, n, K).total;
+    return LF_OK;
+}
+
+int lf_adj_forward(lf_ctx *c, int64_t n, int K, const double *w, void *adj_ws, size_t ws_bytes,
+                   double *loss)
+{
+    if (!c || !w || !loss) return fail(LF_EINVAL, "NULL argument");
+    if (!c->inited || c->hstep != 0) return fail(LF_ESTATE, "lf_adj_forward needs a context just initialised");
+    if (n < 1 || K < 1) return fail(LF_EINVAL, "n and K must be >= 1");
+    int rc;
+    if ((rc = check_ptr(adj_ws, "adjoint workspace"))) return rc;
+    AdjLayout L = adj_layout(&c->p, n, K);
+    if (ws_bytes < L.total) return fail(LF_ENOMEM, "adjoint workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    char *ws = (char *)adj_ws;
+    c->adj_ws = ws;
+    c->adj_n = n;
+    c->adj_K = K;
+    for (int i = 0; i < 4; ++i) c->adj_w[i] = w[i];
+    for (int64_t s = 0; s < L.nck; ++s) {
+        if ((rc = save_slot(c, ws + L.ck + s * L.slot_bytes, L))) return rc;
+        const int64_t m = (n - s * K) < K ? (n - s * K) : K;
+        if ((rc = lf_step(c, m))) return rc;
+    }
+    lf_report rep;
+    if ((rc = lf_energies(c, &rep))) return rc;
+    *loss = w[0] * rep.K[0] + w[1] * rep.K[1] + w[2] * rep.Gr[0] + w[3] * rep.Gr[1];
+    c->adj_ready = 1;
+    return LF_OK;
+}
+
+int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2, void *g_v1, void *g_v2,
+                    double *dL_da0, double *dL_dad0)
+{
+    if (!c || !dL_dG || !dL_da0 || !dL_dad0) return fail(LF_EINVAL, "NULL argument");
+    if (!c->adj_ready) return fail(LF_ESTATE, "lf_adj_backward needs a preceding lf_adj_forward");
+    void *go[4] = {g_f1, g_f2, g_v1, g_v2};
+    int rc;
+    for (int j = 0; j < 4; ++j)
+        if ((rc = check_ptr(go[j], "gradient array"))) return rc;
+    const int64_t n = c->adj_n;
+    const int K = c->adj_K;
+    AdjLayout L = adj_layout(&c->p, n, K);
+    char *ws = c->adj_ws;
+    const size_t n3 = (size_t)c->p.N * c->p.N * c->p.N;
+    const size_t lam_bytes = align_up(n3 * sizeof(double));
+    double *lam[2][4];
+    for (int b = 0; b < 2; ++b)
+        for (int j = 0; j < 4; ++j) lam[b][j] = (double *)(ws + L.lam + (b * 4 + j) * lam_bytes);
+    double *part = (double *)(ws + L.part), *A = (double *)(ws + L.A), *cf = (double *)(ws + L.cf);
+    double *wd = (double *)(ws + L.w);
+    double hw[8] = {0};
+    for (int i = 0; i < 4; ++i) hw[i] = dL * c->adj_w[i];
+    HIPCHK(hipMemcpyAsync(wd, hw, sizeof hw, hipMemcpyHostToDevice, c->stream));
+    // seed: cotangent of the final state
+    const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
+    launch_adj_seed(c->p.dtype, s4, c->p.N, c->P, c->S, wd, lam[0], part, kRedBlocks, A, c->stream);
+    HIPCHK(hipGetLastError());
+    int li = 0;
+    const size_t bytes = n3 * esize(c->p.dtype);
+    DevScalars *tape = (DevScalars *)(ws + L.tape);
+    for (int64_t s = L.nck - 1; s >= 0; --s) {
+        if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, L))) return rc;
+        const int64_t m = (n - s * K) < K ? (n - s * K) : K;
+        for (int64_t j = 0; j < m; ++j) {
+            char *dst = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
+            for (int q = 0; q < 4; ++q)
+                HIPCHK(hipMemcpyAsync(dst + q * L.arr_bytes, c->buf[c->cur][q], bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+            enqueue_step(c, c->cur, c->stream, nullptr);
+            c->cur ^= 1;
+        }
+        for (int64_t j = m - 1; j >= 0; --j) {
+            const char *src = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
+            launch_adj_step(c->p.dtype, src, src + L.arr_bytes, c->p.N, c->p.beta, c->P, tape + j, c->p.dt,
+                            lam[li], lam[li ^ 1], part, kRedBlocks, A, cf, c->stream);
+            li ^= 1;
+        }
+        HIPCHK(hipGetLastError());
+    }
+    launch_adj_desync(c->p.N, c->p.dt, lam[li], A, c->stream);
+    for (int j = 0; j < 4; ++j)
+        HIPCHK(hipMemcpyAsync(go[j], lam[li][j], n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    double hA[4];
+    HIPCHK(hipMemcpyAsync(hA, A, sizeof hA, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *dL_da0 = hA[0];
+    *dL_dad0 = hA[1];
+    *dL_dG = hA[2];
+    c->adj_ready = 0;
+    c->hstep = -1;  // the state is no longer the forward's: re-initialise before reuse
     return LF_OK;
 }
 

@@ -97,6 +97,15 @@ void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void 
                        int N, const DevParams *P, const DevScalars *S, int synchronized,
                        hipStream_t st);
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st);
+// adjoint (lf_adjoint.hip)
+constexpr int kNAdjPart = 7;
+void launch_adj_seed(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
+                     const double *w, double *const lam[4], double *part, int nblk, double *A,
+                     hipStream_t st);
+void launch_adj_step(int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
+                     const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
+                     double *part, int nblk, double *A, double *cf, hipStream_t st);
+void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStream_t st);
 void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st);
 
 }  // namespace lf

@@ -147,6 +147,59 @@ class Lattice:
         check(lib().lf_set_state(self._ctx, *ptrs, ctypes.byref(scalars)))
 
 
+    # ------------------------------------------------------------ adjoint
+    def adjoint_forward(self, n: int, K: int, weights=(0.0, 1.0, 0.0, 1.0)) -> float:
+        """Run n steps with checkpoints every K steps; returns the loss
+        w0 K1 + w1 K2 + w2 G1 + w3 G2 at the end (synchronised energies)."""
+        size = ctypes.c_size_t()
+        check(lib().lf_adj_workspace_bytes(ctypes.byref(self.params), int(n), int(K), ctypes.byref(size)))
+        self.adj_ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        w = (ctypes.c_double * 4)(*[float(x) for x in weights])
+        loss = ctypes.c_double()
+        check(lib().lf_adj_forward(self._ctx, int(n), int(K), w, ctypes.c_void_p(self.adj_ws.data_ptr()),
+                                   size.value, ctypes.byref(loss)))
+        return loss.value
+
+    def adjoint_backward(self, dL: float = 1.0) -> dict:
+        """Gradient of dL * loss: dict(G, a0, ad0 floats; f1, f2, v1, v2 FP64 tensors
+        with respect to the synchronised initial state)."""
+        g = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(4)]
+        ptrs = [_dev_ptr(t, torch.float64, self.shape) for t in g]
+        dG, da0, dad0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().lf_adj_backward(self._ctx, float(dL), ctypes.byref(dG), *ptrs, ctypes.byref(da0),
+                                    ctypes.byref(dad0)))
+        self.adj_ws = None
+        return dict(G=dG.value, a0=da0.value, ad0=dad0.value, f1=g[0], f2=g[1], v1=g[2], v2=g[3])
+
+
+class LeapfrogLoss(torch.autograd.Function):
+    """Loss of the synchronised energies after n leapfrog steps as a
+    differentiable function of G (a 0-d tensor) and the initial fields.
+
+    forward(G, f1, f2, v1, v2, spec) -> loss (0-d FP64 tensor), where spec is
+    a dict with the Lattice arguments (N, L, dt, beta, c1, r, s, kappa2,
+    dtype) and n, K, a0, ad0, weights.  The gradient runs liblf's adjoint
+    kernels (reverse steps with checkpoints every K steps)."""
+
+    @staticmethod
+    def forward(ctx, G, f1, f2, v1, v2, spec):
+        kw = {k: spec[k] for k in ("N", "L", "dt", "beta", "c1", "r", "s", "kappa2")}
+        lat = Lattice(**kw, G=float(G), dtype=spec.get("dtype", torch.float32), device=f1.device)
+        lat.init(f1.detach(), f2.detach(), v1.detach(), v2.detach(), spec["a0"], spec["ad0"])
+        loss = lat.adjoint_forward(spec["n"], spec["K"], spec.get("weights", (0.0, 1.0, 0.0, 1.0)))
+        ctx.lat = lat
+        ctx.dtypes = (f1.dtype, f2.dtype, v1.dtype, v2.dtype)
+        ctx.G_device = G.device if isinstance(G, torch.Tensor) else torch.device("cpu")
+        return torch.tensor(loss, dtype=torch.float64, device=f1.device)
+
+    @staticmethod
+    def backward(ctx, grad):
+        g = ctx.lat.adjoint_backward(float(grad))
+        ctx.lat.close()
+        out = [g[k].to(dt) for k, dt in zip(("f1", "f2", "v1", "v2"), ctx.dtypes)]
+        return (torch.tensor(g["G"], dtype=torch.float64, device=ctx.G_device), *out, None)
+
+
 def _report_dict(rep: Report) -> dict:
     return dict(step=rep.step, a=rep.a, ad=rep.ad, hubble=rep.hubble, K1=rep.K[0], K2=rep.K[1],
                 G1=rep.Gr[0], G2=rep.Gr[1], P=rep.P, rho=rep.rho, R=rep.R, status=rep.status)
