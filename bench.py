@@ -15,7 +15,6 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,17 +31,10 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def sweep_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("lf_sweep.hip", "lf_internal.h"):
-        with open(os.path.join(ROOT, "paper_0911_5692_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(workload: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     or None when it is missing or was taken on a different sweep source."""
+    from paper_0911_5692_amd.profile_sweep import sweep_source_hash
     path = os.path.join(ROOT, "profiles", f"sweep_traffic_{workload}.json")
     try:
         with open(path) as fh:
@@ -81,6 +73,8 @@ def main() -> int:
     ap.add_argument("--kernel-steps", type=int, default=50,
                     help="eager steps timed per kernel with HIP events (roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-run the launch-shape autotuner instead of the committed shape")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -88,7 +82,6 @@ def main() -> int:
               "(see DESIGN.md), not an implementation. Run with --gpus 1.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_0911_5692_amd import Lattice
@@ -102,7 +95,13 @@ def main() -> int:
     ic = W.make_inputs(w)
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
 
-    lat = Lattice(**w.model(), dtype=dtype, device="cuda:0")
+    shape = dict(W.BENCH_SHAPES.get(w.name, {}))
+    if args.autotune:
+        from paper_0911_5692_amd import autotune
+        t = autotune(**w.model(), dtype=dtype, cache_path=None)
+        shape = {k: t[k] for k in ("tile_x", "tile_y", "zchunk")}
+        log(f"autotuned shape {shape} ({t['ms']:.4f} ms/step)")
+    lat = Lattice(**w.model(), dtype=dtype, device="cuda:0", **shape)
     dev = [torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")]
     ad0 = lat.init_physical(*dev, ic["a0"])
     del dev
@@ -156,7 +155,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{w.name}: m^2 phi^2 + g^2 phi^2 chi^2 (G=2.5e5), {w.N}^3 periodic, "
                                f"L={w.L}, dt={w.dt}, vacuum fluctuations, seed [3,0,i,k]",
-                   "N": w.N, "sites": w.sites, "lattice_dtype": w.dtype,
+                   "N": w.N, "sites": w.sites, "lattice_dtype": w.dtype, "launch_shape": shape,
                    "step_hbm_frac_algorithmic": round(value * 1e9 * 8 * esize / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

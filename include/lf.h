@@ -190,6 +190,22 @@ int lf_set_coupling(lf_ctx *ctx, double G);
  * enqueued, in ms (blocking; 0 if none). */
 int lf_last_step_ms(lf_ctx *ctx, double *ms);
 
+/* ---- autotuner ---------------------------------------------------------- */
+
+/* Workspace for lf_autotune with these parameters (largest candidate). */
+int lf_autotune_workspace_bytes(const lf_params *p, size_t *out_bytes);
+/* Pick the sweep launch shape (tile_x, tile_y, zchunk) for p's lattice size,
+ * dtype and beta on the current device.  If cache_path (may be NULL) holds a
+ * line for (device architecture, N, dtype, beta), that choice is returned
+ * (*best_ms = -1).  Otherwise every candidate (the plain sweep; LDS tiles
+ * 64x4, 64x8, 64x16, 128x4, 128x8; z-chunks from the resident-grid rule, 16,
+ * 32, 64, 128, N/4, N/2) is timed with HIP events over graph-replayed steps
+ * of a synthetic state, the fastest is returned in *best (p with the shape
+ * filled in) and appended to the cache as one JSON object per line.  The
+ * caller's workspace (lf_autotune_workspace_bytes) is overwritten. */
+int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_bytes,
+                const char *cache_path, lf_params *best, double *best_ms);
+
 /* ---- adjoint (reverse-mode gradient) ------------------------------------ */
 
 /* Loss E = w[0] K_1 + w[1] K_2 + w[2] Gr_1 + w[3] Gr_2 of the synchronised

@@ -12,11 +12,11 @@ from __future__ import annotations
 
 import importlib
 
-__all__ = ["Lattice", "Ensemble", "LeapfrogLoss", "LfError", "inputs", "workloads", "build"]
+__all__ = ["Lattice", "Ensemble", "LeapfrogLoss", "autotune", "LfError", "inputs", "workloads", "build"]
 
 
 def __getattr__(name):
-    if name in ("Lattice", "Ensemble", "LeapfrogLoss"):
+    if name in ("Lattice", "Ensemble", "LeapfrogLoss", "autotune"):
         return getattr(importlib.import_module(".lattice", __name__), name)
     if name == "LfError":
         return importlib.import_module("._lib", __name__).LfError

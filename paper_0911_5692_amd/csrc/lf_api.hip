@@ -732,6 +732,168 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+struct TuneKey {
+    char arch[64];
+    int N, dtype, beta;
+};
+
+int current_arch(char *arch, size_t n)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LF_EHIP, "no HIP device for the autotuner");
+    }
+    snprintf(arch, n, "%s", prop.gcnArchName);
+    for (char *c = arch; *c; ++c)
+        if (*c == ':') { *c = 0; break; }
+    return LF_OK;
+}
+
+// Cache: one JSON object per line,
+// {"arch": "gfx950", "N": 512, "dtype": 0, "beta": 2, "tile_x": 128, "tile_y": 8, "zchunk": 256, "ms": 0.87}
+int cache_lookup(const char *path, const TuneKey &k, lf_params *best)
+{
+    if (!path) return 0;
+    FILE *f = fopen(path, "r");
+    if (!f) return 0;
+    char line[512];
+    int found = 0;
+    while (fgets(line, sizeof line, f)) {
+        char arch[64] = {0};
+        int N, dt, beta, tx, ty, zc;
+        double ms;
+        if (sscanf(line, " {\"arch\": \"%63[^\"]\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"tile_x\": %d, "
+                         "\"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf", arch, &N, &dt, &beta, &tx, &ty, &zc, &ms) == 8 &&
+            !strcmp(arch, k.arch) && N == k.N && dt == k.dtype && beta == k.beta) {
+            best->tile_x = tx;
+            best->tile_y = ty;
+            best->zchunk = zc;
+            found = 1;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_append(const char *path, const TuneKey &k, const lf_params *b, double ms)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"arch\": \"%s\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"tile_x\": %d, \"tile_y\": %d, "
+               "\"zchunk\": %d, \"ms\": %.6f}\n", k.arch, k.N, k.dtype, k.beta, b->tile_x, b->tile_y, b->zchunk, ms);
+    fclose(f);
+}
+
+// Candidate launch shapes: the plain sweep, every LDS tile, and z-chunks from
+// the resident-grid choice, fixed depths and fractions of N.
+int candidates(const lf_params *p, lf_params *out, int cap)
+{
+    int n = 0;
+    lf_params q = *p;
+    q.tile_x = 0; q.tile_y = 1; q.zchunk = 0;
+    out[n++] = q;
+    const int tiles[5][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}};
+    for (int t = 0; t < 5; ++t) {
+        const int zs[7] = {0, 16, 32, 64, 128, p->N / 4, p->N / 2};
+        int seen[8], ns = 0;
+        for (int j = 0; j < 7; ++j) {
+            q = *p;
+            q.tile_x = tiles[t][0];
+            q.tile_y = tiles[t][1];
+            q.zchunk = zs[j];
+            if (zs[j] != 0 && (zs[j] < 8 || zs[j] > p->N)) continue;
+            const int eff = shape_of(&q).zchunk;
+            int dup = 0;
+            for (int i = 0; i < ns; ++i) dup |= seen[i] == eff;
+            if (dup || n >= cap) continue;
+            seen[ns++] = eff;
+            q.zchunk = eff;
+            out[n++] = q;
+        }
+    }
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_autotune_workspace_bytes(const lf_params *p, size_t *out_bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    lf_params cand[64];
+    const int n = candidates(p, cand, 64);
+    size_t m = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t b = layout_of(&cand[i]).total;
+        m = b > m ? b : m;
+    }
+    *out_bytes = m;
+    return LF_OK;
+}
+
+int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_bytes, const char *cache_path,
+                lf_params *best, double *best_ms)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!best) return fail(LF_EINVAL, "best is NULL");
+    TuneKey k{};
+    if ((rc = current_arch(k.arch, sizeof k.arch))) return rc;
+    k.N = p->N;
+    k.dtype = p->dtype;
+    k.beta = p->beta;
+    *best = *p;
+    if (cache_lookup(cache_path, k, best)) {
+        if (best_ms) *best_ms = -1.0;
+        return validate(best);
+    }
+    size_t need = 0;
+    if ((rc = lf_autotune_workspace_bytes(p, &need))) return rc;
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+    if (ws_bytes < need) return fail(LF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    lf_params cand[64];
+    const int n = candidates(p, cand, 64);
+    double bms = 1e300;
+    int bi = -1;
+    const int steps = p->N >= 256 ? 10 : 40;
+    for (int i = 0; i < n; ++i) {
+        lf_ctx *c = nullptr;
+        if ((rc = lf_create(&cand[i], stream, workspace, ws_bytes, &c))) return rc;
+        void *s4[4] = {c->buf[0][0], c->buf[0][1], c->buf[0][2], c->buf[0][3]};
+        launch_fill_synthetic(c->p.dtype, s4, c->p.N, c->S, c->stream);
+        launch_reduce(c->p.dtype, s4[0], s4[1], c->p.N, c->S->bg_f, c->p.beta, c->part, c->sh.rows, c->stream);
+        c->inited = 1;
+        c->cur = 0;
+        double ms = 0.0;
+        rc = lf_step(c, 3);
+        if (!rc) rc = lf_step(c, steps);
+        if (!rc) rc = lf_last_step_ms(c, &ms);
+        lf_destroy(c);
+        if (rc) return rc;
+        ms /= steps;
+        if (ms < bms) {
+            bms = ms;
+            bi = i;
+        }
+    }
+    *best = cand[bi];
+    if (best_ms) *best_ms = bms;
+    cache_append(cache_path, k, best, bms);
+    return LF_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- ensemble
 
 struct lf_ens {

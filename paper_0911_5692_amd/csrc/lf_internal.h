@@ -97,6 +97,7 @@ void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void 
                        int N, const DevParams *P, const DevScalars *S, int synchronized,
                        hipStream_t st);
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st);
+void launch_fill_synthetic(int dtype, void *const s4[4], int N, DevScalars *S, hipStream_t st);
 // adjoint (lf_adjoint.hip)
 constexpr int kNAdjPart = 7;
 void launch_adj_seed(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,

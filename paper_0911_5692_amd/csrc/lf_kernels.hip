@@ -414,13 +414,54 @@ __global__ void __launch_bounds__(256) k_get_fields(const T *__restrict__ d1, co
     }
 }
 
-// ---------------------------------------------------------------- launchers
-
 static int grid_for(int64_t n, int per_block, int cap)
 {
     int64_t g = (n + per_block - 1) / per_block;
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
+
+// ---------------------------------------------------------------- synthetic state
+
+// A deterministic small-amplitude state for timing runs (autotuner): hash
+// noise of amplitude 1e-4 around f_bar = (1, 0), v_bar = (0, 0), a = 1, a' = 1/2.
+__device__ inline double hash01(uint64_t x)
+{
+    x ^= x >> 33; x *= 0xff51afd7ed558ccdULL; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL; x ^= x >> 33;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_synthetic(T *d1, T *d2, T *e1, T *e2, int N, DevScalars *S)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        d1[i] = (T)(2e-4 * hash01(4 * i));
+        d2[i] = (T)(2e-4 * hash01(4 * i + 1));
+        e1[i] = (T)(2e-4 * hash01(4 * i + 2));
+        e2[i] = (T)(2e-4 * hash01(4 * i + 3));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->a_half = 1.0; S->ad = 0.5;
+        S->bg_f[0] = 1.0; S->bg_f[1] = 0.0; S->bg_v[0] = 0.0; S->bg_v[1] = 0.0;
+        S->step = 0; S->status = 0;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_fill_synthetic(int dtype, void *const s4[4], int N, DevScalars *S, hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const int g = grid_for(N3, 256, 65536);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_fill_synthetic<float>, dim3(g), dim3(256), 0, st, (float *)s4[0], (float *)s4[1],
+                           (float *)s4[2], (float *)s4[3], N, S);
+    else
+        hipLaunchKernelGGL(k_fill_synthetic<double>, dim3(g), dim3(256), 0, st, (double *)s4[0], (double *)s4[1],
+                           (double *)s4[2], (double *)s4[3], N, S);
+}
+
 
 void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
                           const void *v2, int N, int beta, double *part, int nblk, hipStream_t st)

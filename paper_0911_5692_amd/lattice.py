@@ -6,6 +6,7 @@ stream; every step of the evolution runs in liblf's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -24,6 +25,29 @@ def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, shape) -> ctypes.c_void_p:
     if t.data_ptr() % 256:
         raise ValueError("tensor storage must be 256-byte aligned")
     return ctypes.c_void_p(t.data_ptr())
+
+
+DEFAULT_TUNE_CACHE = os.environ.get(
+    "LF_AUTOTUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.jsonl"))
+
+
+def autotune(N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float, s: float,
+             kappa2: float, dtype: torch.dtype = torch.float32, device="cuda",
+             cache_path: str | None = DEFAULT_TUNE_CACHE) -> dict:
+    """Fastest sweep launch shape for this lattice size, dtype and beta on the
+    current device (liblf's lf_autotune; cached per architecture in a JSONL
+    file).  Returns dict(tile_x, tile_y, zchunk, ms) (ms = -1 on a cache hit)."""
+    p = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1), float(G), float(r),
+               float(s), float(kappa2), 0, 0, 0, 0)
+    size = ctypes.c_size_t()
+    check(lib().lf_autotune_workspace_bytes(ctypes.byref(p), ctypes.byref(size)))
+    ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    best, ms = Params(), ctypes.c_double()
+    check(lib().lf_autotune(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(ws.data_ptr()),
+                            size.value, cache_path.encode() if cache_path else None, ctypes.byref(best),
+                            ctypes.byref(ms)))
+    return dict(tile_x=best.tile_x, tile_y=best.tile_y, zchunk=best.zchunk, ms=ms.value)
 
 
 def _aligned(t: torch.Tensor) -> torch.Tensor:

@@ -1,0 +1,165 @@
+"""HBM traffic of the fused sweep from rocprofv3 counters.
+
+Two steps, each its own process:
+
+  run        a plain device copy of known size (the counter calibration),
+             then a few leapfrog steps of a workload at its benchmark launch
+             shape; meant to run under
+               rocprofv3 --pmc FETCH_SIZE ...   and again with   --pmc WRITE_SIZE
+  summarize  reads the two counter CSVs (and optionally a --kernel-trace
+             --stats CSV), scales each counter by what it reads for the copy,
+             and writes profiles/sweep_traffic_<workload>.json and .md.
+
+FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  The calibration factor of
+a counter is (bytes the copy moves) / (what the counter reads for the copy).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+COPY_MIB = 1024
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lf_sweep.hip", "lf_internal.h"):
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run(workload: str, steps: int) -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_0911_5692_amd import Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    w = W.WORKLOADS[workload]
+    shape = W.BENCH_SHAPES.get(w.name, {})
+    n = COPY_MIB * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)  # the calibration copy: reads and writes COPY_MIB MiB
+    torch.cuda.synchronize()
+    del a, b
+    N = w.N
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    f = [1 + 1e-4 * torch.randn((N, N, N), dtype=torch.float64, device="cuda", generator=g),
+         1e-5 * torch.randn((N, N, N), dtype=torch.float64, device="cuda", generator=g),
+         -0.7 + 1e-4 * torch.randn((N, N, N), dtype=torch.float64, device="cuda", generator=g),
+         1e-3 * torch.randn((N, N, N), dtype=torch.float64, device="cuda", generator=g)]
+    lat = Lattice(**w.model(), dtype=torch.float32 if w.dtype == "f32" else torch.float64, **shape)
+    lat.init_physical(*f, 1.0)
+    del f
+    lat.step(steps)
+    torch.cuda.synchronize()
+    print(f"profile run done: {workload} {steps} steps, shape {shape}", flush=True)
+
+
+def _rows(path: str):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d: str, suffix: str) -> str:
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"{suffix} under {d}")
+
+
+def _counter(path: str, name: str, kernel_pred):
+    vals = [float(r["Counter_Value"]) for r in _rows(path)
+            if r["Counter_Name"] == name and kernel_pred(r["Kernel_Name"])]
+    return vals
+
+
+def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | None, out_dir: str,
+              commands: list[str]) -> dict:
+    sys.path.insert(0, ROOT)
+    from paper_0911_5692_amd import workloads as W
+
+    w = W.WORKLOADS[workload]
+    esize = 4 if w.dtype == "f32" else 8
+    alg = 8 * esize * w.sites
+    copy_bytes = COPY_MIB * (1 << 20)
+    is_copy = lambda k: "copy" in k.lower() and "lf::" not in k
+    is_sweep = lambda k: "k_sweep" in k
+    fpath, wpath = _find(fetch_dir, "counter_collection.csv"), _find(write_dir, "counter_collection.csv")
+    f_copy = _counter(fpath, "FETCH_SIZE", is_copy)
+    w_copy = _counter(wpath, "WRITE_SIZE", is_copy)
+    f_sweep = _counter(fpath, "FETCH_SIZE", is_sweep)
+    w_sweep = _counter(wpath, "WRITE_SIZE", is_sweep)
+    # the calibration copy is the largest copy dispatch
+    fc, wc = max(f_copy) * 1024.0, max(w_copy) * 1024.0
+    kf, kw = copy_bytes / fc, copy_bytes / wc
+    fetch = sum(f_sweep) / len(f_sweep) * 1024.0 * kf
+    write = sum(w_sweep) / len(w_sweep) * 1024.0 * kw
+    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(), algorithmic_bytes_per_launch=alg,
+               fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
+               hbm_bytes_per_launch=fetch + write, fetch_calibration=kf, write_calibration=kw,
+               fetch_over_algorithmic_reads=fetch / (alg / 2), write_over_algorithmic_writes=write / (alg / 2),
+               launches=len(f_sweep))
+    if trace_dir:
+        stats = _rows(_find(trace_dir, "kernel_stats.csv"))
+        res["kernel_stats"] = [dict(name=r["Name"][:90], calls=int(r["Calls"]), avg_ns=float(r["AverageNs"]),
+                                    pct=float(r["Percentage"])) for r in stats[:8]]
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"sweep_traffic_{workload}.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    with open(os.path.join(out_dir, f"sweep_traffic_{workload}.md"), "w") as fh:
+        fh.write(f"# HBM traffic of the fused sweep, workload {workload}\n\n")
+        fh.write("Commands (from the repository root on the GPU host):\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write(f"\nCalibration: a device copy of {COPY_MIB} MiB reads FETCH_SIZE = {fc / 1024:.1f} KiB "
+                 f"and WRITE_SIZE = {wc / 1024:.1f} KiB, so the counters are scaled by "
+                 f"{kf:.4f} (fetch) and {kw:.4f} (write).\n\n")
+        fh.write("| quantity | per sweep launch |\n|---|---|\n")
+        fh.write(f"| algorithmic bytes (32 B/site FP32) | {alg / 1e9:.4f} GB |\n")
+        fh.write(f"| HBM fetch (scaled) | {fetch / 1e9:.4f} GB = {res['fetch_over_algorithmic_reads']:.3f} x algorithmic reads |\n")
+        fh.write(f"| HBM write (scaled) | {write / 1e9:.4f} GB = {res['write_over_algorithmic_writes']:.3f} x algorithmic writes |\n")
+        fh.write(f"| total HBM traffic | {(fetch + write) / 1e9:.4f} GB |\n")
+        fh.write(f"| sweep launches averaged | {len(f_sweep)} |\n")
+        fh.write(f"| sweep source hash | {res['sweep_source_hash']} |\n")
+        if trace_dir:
+            fh.write("\nKernel trace (rocprofv3 --kernel-trace --stats):\n\n| kernel | calls | avg ns | % |\n|---|---|---|---|\n")
+            for k in res["kernel_stats"]:
+                fh.write(f"| {k['name']} | {k['calls']} | {k['avg_ns']:.0f} | {k['pct']:.1f} |\n")
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--workload", default="m2phi2_512c_f32")
+    r.add_argument("--steps", type=int, default=4)
+    s = sub.add_parser("summarize")
+    s.add_argument("--workload", default="m2phi2_512c_f32")
+    s.add_argument("--fetch-dir", required=True)
+    s.add_argument("--write-dir", required=True)
+    s.add_argument("--trace-dir")
+    s.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
+    s.add_argument("--command", action="append", default=[])
+    a = ap.parse_args()
+    if a.cmd == "run":
+        run(a.workload, a.steps)
+    else:
+        res = summarize(a.workload, a.fetch_dir, a.write_dir, a.trace_dir, a.out_dir, a.command)
+        print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -91,6 +91,12 @@ def ensemble_members():
 
 WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5)}
 
+# Sweep launch shapes used by the benchmark, as chosen by lf_autotune on an
+# MI355X (gfx950); re-run the autotuner (bench.py --autotune) on other parts.
+BENCH_SHAPES = {
+    CFG3.name: dict(tile_x=128, tile_y=8, zchunk=64),
+}
+
 
 def make_inputs(w: Workload, realization: int = 0) -> dict:
     """Initial fields f1, f2 and rescaled physical velocities u1, u2 (float64),

@@ -78,3 +78,27 @@ def test_create_argument_checks_before_any_device_call(LB):
                          ctypes.byref(ctx)) == LB.LF_ENOMEM
     assert lib.lf_step(None, 1) == LB.LF_EINVAL
     assert lib.lf_destroy(None) == LB.LF_OK
+
+
+def test_autotune_workspace_covers_every_candidate(LB):
+    lib = LB.lib()
+    p = _params(LB, N=48)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lf_autotune_workspace_bytes(ctypes.byref(p), ctypes.byref(a)) == 0
+    assert lib.lf_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == 0
+    assert a.value >= b.value
+    size = ctypes.c_size_t()
+    assert lib.lf_adj_workspace_bytes(ctypes.byref(p), 100, 7, ctypes.byref(size)) == 0
+    assert size.value > 7 * 4 * 48 ** 3 * 4
+    assert lib.lf_adj_workspace_bytes(ctypes.byref(p), 0, 7, ctypes.byref(size)) == LB.LF_EINVAL
+
+
+def test_ensemble_workspace_and_validation(LB):
+    lib = LB.lib()
+    arr = (LB.Params * 3)(_params(LB, N=16), _params(LB, N=24), _params(LB, N=40))
+    size = ctypes.c_size_t()
+    assert lib.lf_ens_workspace_bytes(3, arr, ctypes.byref(size)) == 0
+    assert size.value > 8 * (16 ** 3 + 24 ** 3 + 40 ** 3) * 4
+    bad = (LB.Params * 2)(_params(LB, N=16), _params(LB, N=16, dtype=1))
+    assert lib.lf_ens_workspace_bytes(2, bad, ctypes.byref(size)) == LB.LF_EINVAL
+    assert lib.lf_ens_workspace_bytes(0, arr, ctypes.byref(size)) == LB.LF_EINVAL
