@@ -136,7 +136,7 @@ __device__ inline int xcd_remap(int b, int nb)
 
 // One block's work: the tile x0.., y0.. of an N^3 lattice over planes
 // [z0, z1), writing its four partial sums to part_row[0..3].
-template <typename T, int NH, int TX, int TY>
+template <typename T, int NH, int TX, int TY, int PF>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__restrict__ d2,
                                            const T *__restrict__ e1, const T *__restrict__ e2,
                                            T *__restrict__ d1n, T *__restrict__ d2n,
@@ -210,10 +210,37 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         return p + (int64_t)zw * NN;
     };
 
-    // register queues: d at z-1, z, z+1 and e at z, for both fields
+    // register queues: d at z-1, z, z+1 and e at z, for both fields; PF
+    // prefetch slots: slot j holds d(z+2+j), e(z+1+j) and the halo of plane
+    // z+2+j at the start of iteration z
     T qm1[KI], qc1[KI], qp1[KI], qm2[KI], qc2[KI], qp2[KI], ev1[KI], ev2[KI], dn1[KI], dn2[KI];
     T rqm1 = 0, rqc1 = 0, rqp1 = 0, rqm2 = 0, rqc2 = 0, rqp2 = 0, rev1 = 0, rev2 = 0;
     T hv1[2] = {0, 0}, hv2[2] = {0, 0};  // halo of the plane staged next
+    T sd1[PF][KI], sd2[PF][KI], se1[PF][KI], se2[PF][KI];
+    T srd1[PF], srd2[PF], sre1[PF], sre2[PF], sh1[PF][2], sh2[PF][2];
+    // load prefetch slot j with d(pz), e(pz - 1), halo(pz); planes beyond the
+    // chunk's needs are skipped
+    auto fill = [&](int j, int pz) {
+        const bool need_d = pz <= z1, need_e = pz - 1 <= z1 - 1, need_h = pz <= z1 - 1;
+        const T *a1 = plane(d1, pz), *a2 = plane(d2, pz);
+        const T *b1 = plane(e1, pz - 1), *b2 = plane(e2, pz - 1);
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            sd1[j][k] = need_d ? a1[goff[k]] : T(0);
+            sd2[j][k] = need_d ? a2[goff[k]] : T(0);
+            se1[j][k] = need_e ? b1[goff[k]] : T(0);
+            se2[j][k] = need_e ? b2[goff[k]] : T(0);
+        }
+        srd1[j] = (hasr && need_d) ? a1[roff] : T(0);
+        srd2[j] = (hasr && need_d) ? a2[roff] : T(0);
+        sre1[j] = (hasr && need_e) ? b1[roff] : T(0);
+        sre2[j] = (hasr && need_e) ? b2[roff] : T(0);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            sh1[j][m] = (hash[m] && need_h) ? a1[hoff[m]] : T(0);
+            sh2[j][m] = (hash[m] && need_h) ? a2[hoff[m]] : T(0);
+        }
+    };
     {
         const T *m1 = plane(d1, z0 - 2), *m2 = plane(d2, z0 - 2);
         const T *c1p = plane(d1, z0 - 1), *c2p = plane(d2, z0 - 1);
@@ -233,7 +260,9 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
             rqp1 = p1[roff]; rqp2 = p2[roff];
             rev1 = f1[roff]; rev2 = f2[roff];
         }
-        // stage plane z0-1 (buffer 0); its halo is loaded here, the next one ahead
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) fill(j, z0 + 1 + j);
+        // stage plane z0-1 (buffer 0); the halo of plane z0 is staged next
 #pragma unroll
         for (int k = 0; k < KI; ++k) { sd[0][0][lsd[k]] = qc1[k]; sd[0][1][lsd[k]] = qc2[k]; }
         if (hasr) { sd[0][0][rlsd] = rqc1; sd[0][1][rlsd] = rqc2; }
@@ -251,31 +280,11 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     int cur = 0;
     for (int z = z0 - 1; z < z1; ++z, cur ^= 1) {
-        // prefetch: d(z+2) and e(z+1) for the next plane, halo(z+2) for the
-        // plane staged in the next iteration
-        const bool more = (z + 1 < z1);
-        T nd1[KI], nd2[KI], ne1[KI], ne2[KI];
-        T rnd1 = 0, rnd2 = 0, rne1 = 0, rne2 = 0, nh1[2] = {0, 0}, nh2[2] = {0, 0};
-        if (more) {
-            const T *a1 = plane(d1, z + 2), *a2 = plane(d2, z + 2);
-            const T *b1 = plane(e1, z + 1), *b2 = plane(e2, z + 1);
-#pragma unroll
-            for (int k = 0; k < KI; ++k) {
-                nd1[k] = a1[goff[k]]; nd2[k] = a2[goff[k]];
-                ne1[k] = b1[goff[k]]; ne2[k] = b2[goff[k]];
-            }
-            if (hasr) {
-                rnd1 = a1[roff]; rnd2 = a2[roff];
-                rne1 = b1[roff]; rne2 = b2[roff];
-            }
-            if (z + 2 < z1) {
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    if (hash[m]) { nh1[m] = a1[hoff[m]]; nh2[m] = a2[hoff[m]]; }
-            }
-        }
+        // newest prefetch slot: d(z+1+PF), e(z+PF), halo(z+1+PF)
+        fill(PF - 1, z + 1 + PF);
 
         const bool live = (z >= z0);
+        const bool more = (z + 1 < z1);
         const T *s0 = sd[cur][0], *s1 = sd[cur][1];
         T *n0 = sn[cur][0], *n1 = sn[cur][1];
         T *o_e1 = const_cast<T *>(plane(e1n, z)), *o_e2 = const_cast<T *>(plane(e2n, z));
@@ -313,7 +322,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
             n0[rlsn] = rqc1 + c.dt * (rev1 + ia);
             n1[rlsn] = rqc2 + c.dt * (rev2 + ib);
         }
-        // stage plane z+1 into the other buffer (data loaded one iteration ago)
+        // stage plane z+1 into the other buffer (data loaded earlier)
         if (more) {
             T *t0 = sd[cur ^ 1][0], *t1 = sd[cur ^ 1][1];
 #pragma unroll
@@ -342,18 +351,30 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
             }
         }
 
-        // rotate the queues
+        // rotate the queues and the prefetch slots
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
-            qm1[k] = qc1[k]; qc1[k] = qp1[k]; qp1[k] = nd1[k];
-            qm2[k] = qc2[k]; qc2[k] = qp2[k]; qp2[k] = nd2[k];
-            ev1[k] = ne1[k]; ev2[k] = ne2[k];
+            qm1[k] = qc1[k]; qc1[k] = qp1[k]; qp1[k] = sd1[0][k];
+            qm2[k] = qc2[k]; qc2[k] = qp2[k]; qp2[k] = sd2[0][k];
+            ev1[k] = se1[0][k]; ev2[k] = se2[0][k];
         }
-        rqm1 = rqc1; rqc1 = rqp1; rqp1 = rnd1;
-        rqm2 = rqc2; rqc2 = rqp2; rqp2 = rnd2;
-        rev1 = rne1; rev2 = rne2;
-        hv1[0] = nh1[0]; hv1[1] = nh1[1];
-        hv2[0] = nh2[0]; hv2[1] = nh2[1];
+        rqm1 = rqc1; rqc1 = rqp1; rqp1 = srd1[0];
+        rqm2 = rqc2; rqc2 = rqp2; rqp2 = srd2[0];
+        rev1 = sre1[0]; rev2 = sre2[0];
+        hv1[0] = sh1[0][0]; hv1[1] = sh1[0][1];
+        hv2[0] = sh2[0][0]; hv2[1] = sh2[0][1];
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                sd1[j][k] = sd1[j + 1][k]; sd2[j][k] = sd2[j + 1][k];
+                se1[j][k] = se1[j + 1][k]; se2[j][k] = se2[j + 1][k];
+            }
+            srd1[j] = srd1[j + 1]; srd2[j] = srd2[j + 1];
+            sre1[j] = sre1[j + 1]; sre2[j] = sre2[j + 1];
+            sh1[j][0] = sh1[j + 1][0]; sh1[j][1] = sh1[j + 1][1];
+            sh2[j][0] = sh2[j + 1][0]; sh2[j][1] = sh2[j + 1][1];
+        }
     }
 
     // block partial sums, fixed order
@@ -377,6 +398,10 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
 #ifndef LF_SWEEP_MIN_WAVES
 #define LF_SWEEP_MIN_WAVES 4
 #endif
+// planes of loads in flight ahead of the plane being computed (1 or 2)
+#ifndef LF_SWEEP_PREFETCH
+#define LF_SWEEP_PREFETCH 1
+#endif
 
 // Single lattice: one block per (tile, z-chunk), XCD-aware tile order.
 template <typename T, int NH, int TX, int TY>
@@ -391,7 +416,7 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_lds(
     const int ty = b % nty;
     const int tz = b / nty;
     const int z0 = tz * zchunk;
-    sweep_tile<T, NH, TX, TY>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, tx * TX, ty * TY, z0,
+    sweep_tile<T, NH, TX, TY, LF_SWEEP_PREFETCH>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, tx * TX, ty * TY, z0,
                               min(z0 + zchunk, N), C, part + (size_t)tile * kNPart);
 }
 
@@ -409,7 +434,7 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_ens(
         const int z0 = tz * e.zchunk;
         const T *const *in = (const T *const *)e.buf[parity];
         T *const *out = (T *const *)e.buf[parity ^ 1];
-        sweep_tile<T, NH, TX, TY>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
+        sweep_tile<T, NH, TX, TY, LF_SWEEP_PREFETCH>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
                                   tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
                                   e.part + (size_t)it.z * kNPart);
         __syncthreads();  // LDS is reused by the next item
