@@ -168,6 +168,13 @@ int lf_step(lf_ctx *ctx, int64_t n);
  * ENONFINITE (after filling *out) if the sticky flag is set. */
 int lf_energies(lf_ctx *ctx, lf_report *out);
 
+/* Energy density and pressure per site at the synchronised time (eq. rho-pres
+ * in program units, the energy-density/pressure computation of Sec. II.C):
+ *   rho = sum_i K_i + Gr_i + V_pr,   p = sum_i K_i - Gr_i/3 - V_pr
+ * with the per-site terms of lf_report.  rho, p: N^3 arrays of out_dtype or
+ * NULL (not written).  avg[3] = <rho>, <p>, w = <p>/<rho>.  Blocking. */
+int lf_rho_p(lf_ctx *ctx, void *rho, void *p, int out_dtype, double *avg);
+
 /* Write the full fields (background + deviation) to caller arrays of element
  * type out_dtype: synchronized = 0 gives the stored f(k+1/2), v(k);
  * synchronized = 1 gives f(k) = f(k+1/2) - dt/2 v(k), v(k).  Any pointer may

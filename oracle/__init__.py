@@ -92,6 +92,7 @@ def lib():
             "orc_evolve": ([_P, vp, vp, vp, vp, vp, vp, i64, vp], None),
             "orc_energy": ([_P, vp, vp, vp, vp, d, d, vp], None),
             "orc_init_physical": ([_P, vp, vp, vp, vp, d], d),
+            "orc_rho_p": ([_P, vp, vp, vp, vp, d, d, vp, vp, vp], None),
             "orcz_desync_state": ([_P, vp, vp, vp, vp, vp, vp, vp], None),
             "orcz_evolve": ([_P, vp, vp, vp, vp, vp, vp, vp, i64], None),
             "orcz_energy": ([_P, vp, vp, vp, vp, vp, vp, vp, vp], None),
@@ -227,6 +228,17 @@ def energies(st: State) -> dict:
     d = dict(zip(ENERGY_KEYS, (float(x) for x in out)))
     d["step"] = st.step
     return d
+
+
+def rho_p(st: State, arrays: bool = True):
+    """Energy density and pressure at the synchronised time (eq. rho-pres in
+    program units): (rho, p) arrays (or None) and dict(rho, p, w) of averages."""
+    out = np.zeros(3)
+    rho = np.empty_like(st.f1) if arrays else None
+    pr = np.empty_like(st.f1) if arrays else None
+    lib().orc_rho_p(ctypes.byref(st.m.c()), _ptr(st.f1), _ptr(st.f2), _ptr(st.v1), _ptr(st.v2),
+                    st.a_half, st.ad, _ptr(rho) if arrays else None, _ptr(pr) if arrays else None, _ptr(out))
+    return rho, pr, dict(rho=float(out[0]), p=float(out[1]), w=float(out[2]))
 
 
 def synchronized_fields(st: State):

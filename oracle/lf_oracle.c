@@ -202,6 +202,49 @@ double orc_init_physical(const orc_params *p, const double *f1, const double *f2
     return ad0;
 }
 
+/* Energy density and pressure per site at the synchronised time (eq. rho-pres
+ * in program units; the same rescaling takes rho and p to rho_pr, p_pr):
+ *   rho(x) = sum_i [K_i(x) + G_i(x)] + V_pr,   p(x) = sum_i [K_i(x) - G_i(x)/3] - V_pr
+ *   K_i = (v_i - r (a'/a) f_i)^2 / 2,   G_i = a^(-2s-2) |grad+ f_i|^2 / 2
+ * with f = f(k+1/2) - dt/2 v(k), a_k = a_{k+1/2} - dt/2 a'_k.  rho, p may be
+ * NULL.  out: <rho>, <p>, w = <p>/<rho>. */
+void orc_rho_p(const orc_params *p, const double *f1, const double *f2, const double *v1,
+               const double *v2, double a_half, double ad, double *rho, double *pr, double *out)
+{
+    const int64_t N = p->N, N3 = N * N * N;
+    const double dx = p->L / (double)N, inv_dx2 = 1.0 / (dx * dx), h = 0.5 * p->dt;
+    const double r = p->r, s = p->s;
+    double *fs = (double *)malloc(2 * N3 * sizeof(double));
+    double *fs1 = fs, *fs2 = fs + N3;
+    const double a = a_half - h * ad, hub = ad / a;
+    for (int64_t i = 0; i < N3; ++i) {
+        fs1[i] = f1[i] - h * v1[i];
+        fs2[i] = f2[i] - h * v2[i];
+    }
+    const double gfac = 0.5 * pow(a, -2.0 * s - 2.0);
+    const double ap1 = pow(a, p1_of(p)), ap2 = pow(a, p2_of(p));
+    double srho = 0.0, sp = 0.0;
+#pragma omp parallel for schedule(static) reduction(+:srho,sp)
+    for (int64_t z = 0; z < N; ++z)
+        for (int64_t y = 0; y < N; ++y)
+            for (int64_t x = 0; x < N; ++x) {
+                int64_t i = IDX(x, y, z, N);
+                double q1 = v1[i] - r * hub * fs1[i], q2 = v2[i] - r * hub * fs2[i];
+                double K = 0.5 * (q1 * q1 + q2 * q2);
+                double G = gfac * (orc_grad2_site(fs1, N, x, y, z, inv_dx2) + orc_grad2_site(fs2, N, x, y, z, inv_dx2));
+                double V = orc_vpr(p, p->G_re, fs1[i], fs2[i], ap1, ap2);
+                double rr = K + G + V, pp = K - G / 3.0 - V;
+                if (rho) rho[i] = rr;
+                if (pr) pr[i] = pp;
+                srho += rr;
+                sp += pp;
+            }
+    out[0] = srho / (double)N3;
+    out[1] = sp / (double)N3;
+    out[2] = out[1] / out[0];
+    free(fs);
+}
+
 /* ---- complex-step entry points ----------------------------------------- */
 /* Same map as orc_desync_state / orc_evolve / orc_energy over complex state
  * and a complex G; arrays are interleaved (re, im) pairs. */

@@ -63,6 +63,7 @@ SIGNATURES = {
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "lf_step": ([_vp, ctypes.c_int64], ctypes.c_int),
     "lf_energies": ([_vp, ctypes.POINTER(Report)], ctypes.c_int),
+    "lf_rho_p": ([_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "lf_get_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "lf_get_state": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Scalars)], ctypes.c_int),
     "lf_set_state": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Scalars)], ctypes.c_int),

@@ -446,6 +446,24 @@ int lf_energies(lf_ctx *c, lf_report *out)
     return LF_OK;
 }
 
+int lf_rho_p(lf_ctx *c, void *rho, void *p, int out_dtype, double *avg)
+{
+    if (!c || !avg) return fail(LF_EINVAL, "NULL argument");
+    if (!c->inited) return fail(LF_ESTATE, "lf_rho_p before lf_init");
+    if (out_dtype != LF_F32 && out_dtype != LF_F64) return fail(LF_EINVAL, "out_dtype=%d", out_dtype);
+    if ((rho && (uintptr_t)rho % kAlign) || (p && (uintptr_t)p % kAlign))
+        return fail(LF_EINVAL, "output arrays must be 256-byte aligned");
+    const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
+    // the energy partial rows (kRedBlocks x kNEn doubles) hold the 2 sums here
+    launch_rho_p(c->p.dtype, out_dtype, s4, rho, p, c->p.N, c->P, c->S, c->enp, kRedBlocks, c->enout, c->stream);
+    HIPCHK(hipGetLastError());
+    double h[3];
+    HIPCHK(hipMemcpyAsync(h, c->enout, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 3; ++i) avg[i] = h[i];
+    return LF_OK;
+}
+
 int lf_get_fields(lf_ctx *c, void *f1, void *f2, void *v1, void *v2, int out_dtype, int synchronized)
 {
     if (!c) return fail(LF_EINVAL, "ctx is NULL");

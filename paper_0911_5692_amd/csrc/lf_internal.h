@@ -93,6 +93,9 @@ int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk);
 int sweep_lds_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);
 void launch_energy(int dtype, const void *const st4[4], int N, const DevParams *P,
                    const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st);
+void launch_rho_p(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+                  const DevParams *P, const DevScalars *S, double *part, int nblk, double *out_dev,
+                  hipStream_t st);
 void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],
                        int N, const DevParams *P, const DevScalars *S, int synchronized,
                        hipStream_t st);

@@ -391,6 +391,71 @@ __global__ void __launch_bounds__(kStage2Threads) k_energy_final(const double *p
     out[11] = (double)bad;
 }
 
+// ---------------------------------------------------------------- rho and p
+
+// Energy density and pressure per site at the synchronised time (eq. rho-pres
+// in program units): rho = sum_i K_i + G_i + V_pr, p = sum_i K_i - G_i/3 - V_pr,
+// K_i = (v_i - r (a'/a) f_i)^2/2, G_i = a^(-2s-2) |grad+ f_i|^2/2.  FP64 per
+// site; rho, p may be NULL.  Partials: sum rho, sum p.
+template <typename T, typename To>
+__global__ void __launch_bounds__(256) k_rho_p(const T *__restrict__ d1, const T *__restrict__ d2,
+                                               const T *__restrict__ e1, const T *__restrict__ e2,
+                                               int N, const DevParams *__restrict__ P,
+                                               const DevScalars *__restrict__ S, To *rho, To *pr,
+                                               double *part)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    const int64_t NN = (int64_t)N * N;
+    const double h = 0.5 * P->dt, r = P->r, s = P->s;
+    const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
+    const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
+    const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
+    const double gfac = 0.5 * pow(ak, -2.0 * s - 2.0) / (P->dx * P->dx);
+    const double cv1 = P->c1 * pow(ak, P->p1) / (double)P->beta, cv2 = 0.5 * P->G * pow(ak, P->p2);
+    const int beta = P->beta;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(i, N, x, y, z);
+        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
+        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
+        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const double s1 = (double)d1[i] - h * (double)e1[i];
+        const double s2 = (double)d2[i] - h * (double)e2[i];
+        const double x1 = gs1 + s1, x2 = gs2 + s2;
+        const double q1 = (vb1 + (double)e1[i]) - r * hub * x1;
+        const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
+        double t0 = ((double)d1[ix] - h * (double)e1[ix]) - s1;
+        double t1 = ((double)d1[iy] - h * (double)e1[iy]) - s1;
+        double t2 = ((double)d1[iz] - h * (double)e1[iz]) - s1;
+        double g = t0 * t0 + t1 * t1 + t2 * t2;
+        t0 = ((double)d2[ix] - h * (double)e2[ix]) - s2;
+        t1 = ((double)d2[iy] - h * (double)e2[iy]) - s2;
+        t2 = ((double)d2[iz] - h * (double)e2[iz]) - s2;
+        g += t0 * t0 + t1 * t1 + t2 * t2;
+        const double K = 0.5 * (q1 * q1 + q2 * q2), Gs = gfac * g;
+        const double V = cv1 * ipow_d(x1, beta) + cv2 * x1 * x1 * x2 * x2;
+        const double rr = K + Gs + V, pp = K - Gs / 3.0 - V;
+        if (rho) rho[i] = (To)rr;
+        if (pr) pr[i] = (To)pp;
+        acc[0] += rr;
+        acc[1] += pp;
+    }
+    block_sum_store<2>(acc, part + (size_t)blockIdx.x * 2);
+}
+
+__global__ void __launch_bounds__(kStage2Threads) k_rho_p_final(const double *part, int nblk,
+                                                                const DevParams *__restrict__ P, double *out)
+{
+    double t[2];
+    stage2_sum<2>(part, nblk, t);
+    if (threadIdx.x != 0) return;
+    out[0] = t[0] / P->N3;
+    out[1] = t[1] / P->N3;
+    out[2] = out[1] / out[0];
+}
+
 // ---------------------------------------------------------------- export
 
 template <typename T, typename To>
@@ -553,6 +618,25 @@ void launch_get_fields(int dtype, int out_dtype, const void *const s4[4], void *
     else if (dtype == 0) get_fields_t<float, double>(s4, out, N, P, S, synchronized, st);
     else if (out_dtype == 0) get_fields_t<double, float>(s4, out, N, P, S, synchronized, st);
     else get_fields_t<double, double>(s4, out, N, P, S, synchronized, st);
+}
+
+template <typename T, typename To>
+static void rho_p_t(const void *const s4[4], void *rho, void *pr, int N, const DevParams *P,
+                    const DevScalars *S, double *part, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rho_p<T, To>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0], (const T *)s4[1],
+                       (const T *)s4[2], (const T *)s4[3], N, P, S, (To *)rho, (To *)pr, part);
+}
+
+void launch_rho_p(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+                  const DevParams *P, const DevScalars *S, double *part, int nblk, double *out_dev,
+                  hipStream_t st)
+{
+    if (dtype == 0 && out_dtype == 0) rho_p_t<float, float>(s4, rho, pr, N, P, S, part, nblk, st);
+    else if (dtype == 0) rho_p_t<float, double>(s4, rho, pr, N, P, S, part, nblk, st);
+    else if (out_dtype == 0) rho_p_t<double, float>(s4, rho, pr, N, P, S, part, nblk, st);
+    else rho_p_t<double, double>(s4, rho, pr, N, P, S, part, nblk, st);
+    hipLaunchKernelGGL(k_rho_p_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, out_dev);
 }
 
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st)

@@ -149,6 +149,15 @@ class Lattice:
                     K2=rep.K[1], G1=rep.Gr[0], G2=rep.Gr[1], P=rep.P, rho=rep.rho, R=rep.R,
                     status=rep.status)
 
+    def rho_p(self, arrays: bool = True, dtype: torch.dtype = torch.float64):
+        """Energy density and pressure at the synchronised time: (rho, p) tensors
+        (or None) and dict(rho, p, w) of volume averages, w = <p>/<rho>."""
+        out = [torch.empty(self.shape, dtype=dtype, device=self.device) for _ in range(2)] if arrays else [None, None]
+        ptrs = [(_dev_ptr(t, dtype, self.shape) if t is not None else None) for t in out]
+        avg = (ctypes.c_double * 3)()
+        check(lib().lf_rho_p(self._ctx, ptrs[0], ptrs[1], _DT[dtype], avg))
+        return out[0], out[1], dict(rho=avg[0], p=avg[1], w=avg[2])
+
     def fields(self, synchronized: bool = False, dtype: torch.dtype = torch.float64):
         """(f1, f2, v1, v2) as new tensors: f(k+1/2) and v(k), or f(k), v(k)."""
         out = [torch.empty(self.shape, dtype=dtype, device=self.device) for _ in range(4)]

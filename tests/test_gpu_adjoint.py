@@ -114,6 +114,6 @@ def test_leapfrog_loss_autograd():
     loss = LeapfrogLoss.apply(G, t1, to_dev(f2), to_dev(v1), to_dev(v2), spec)
     (2.0 * loss).backward()
     ref = O.adjoint(m, f1, f2, v1, v2, 1.0, ad0, 20, wK=WEIGHTS[:2], wG=WEIGHTS[2:])
-    assert abs(float(loss) - ref["E"]) <= 1e-10 * ref["E"]
+    assert abs(loss.item() - ref["E"]) <= 1e-10 * ref["E"]
     assert abs(float(G.grad) - 2.0 * ref["dG"]) <= 1e-9 * abs(2.0 * ref["dG"])
     assert _relmax(t1.grad.cpu().numpy(), 2.0 * ref["f1"]) <= 1e-9

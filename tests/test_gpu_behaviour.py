@@ -170,3 +170,20 @@ def test_step_before_init_is_a_state_error():
     with pytest.raises(LfError) as ei:
         lat.step(-1)
     assert ei.value.code == 1
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_rho_p_matches_oracle(dtype, tol):
+    """Per-site energy density and pressure (the paper's second kernel) and
+    w = <p>/<rho> against the oracle, on the 512^3-model recipe at 48^3."""
+    w = W.CFG3.resized(48)
+    st, _, _, ic = oracle_run(w, 120)
+    rho, p, avg = O.rho_p(st)
+    lat, _ = gpu_run(w, ic, 120, dtype=dtype)
+    grho, gp, gavg = lat.rho_p()
+    assert float(np.max(np.abs(grho.cpu().numpy() - rho)) / np.max(np.abs(rho))) <= tol
+    assert float(np.max(np.abs(gp.cpu().numpy() - p)) / np.max(np.abs(p))) <= tol
+    for k in ("rho", "p", "w"):
+        assert abs(gavg[k] - avg[k]) <= tol * abs(avg[k]), k
+    _, _, only = lat.rho_p(arrays=False)
+    assert only == gavg
