@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("L", ctypes.c_double), ("dt", ctypes.c_double),
-                ("beta", ctypes.c_int32), ("pad_", ctypes.c_int32), ("c1", ctypes.c_double),
+                ("beta", ctypes.c_int32), ("stencil", ctypes.c_int32), ("c1", ctypes.c_double),
                 ("G", ctypes.c_double), ("r", ctypes.c_double), ("s", ctypes.c_double),
                 ("kappa2", ctypes.c_double)]
 
@@ -58,9 +58,10 @@ class Model:
     r: float
     s: float
     kappa2: float
+    stencil: int = 7   # Laplacian: 7 or 27 points (Sec. II.C)
 
     def c(self) -> _Params:
-        return _Params(self.N, self.L, self.dt, self.beta, 0, self.c1, self.G, self.r,
+        return _Params(self.N, self.L, self.dt, self.beta, self.stencil, self.c1, self.G, self.r,
                        self.s, self.kappa2)
 
     def replace(self, **kw) -> "Model":
@@ -125,7 +126,7 @@ def _check(m: Model):
 # ---------------------------------------------------------------- operators
 
 def laplacian(m: Model, f):
-    """7-point Laplacian with 1/dx^2, periodic (Sec. II.C)."""
+    """The model's Laplacian (7 or 27 points) with 1/dx^2, periodic (Sec. II.C)."""
     f = _arr(f)
     out = np.empty_like(f)
     lib().orc_laplacian(ctypes.byref(m.c()), _ptr(f), _ptr(out))
@@ -133,7 +134,8 @@ def laplacian(m: Model, f):
 
 
 def grad2(m: Model, f):
-    """|grad+ f|^2 per site, forward differences with 1/dx^2."""
+    """Gradient energy density per site (Dirichlet form of the Laplacian; for
+    7 points the forward-difference |grad+ f|^2), with 1/dx^2."""
     f = _arr(f)
     out = np.empty_like(f)
     lib().orc_grad2(ctypes.byref(m.c()), _ptr(f), _ptr(out))

@@ -20,7 +20,9 @@
  * Readings of the paper that this code fixes (where the paper is silent or
  * its printed formula is garbled):
  *   - the Laplacian is the 7-point (6-neighbour) one (Sec. II.C names it as
- *     LATTICEEASY's discretisation);
+ *     LATTICEEASY's discretisation) unless the 27-point stencil the paper
+ *     itself uses is selected; the gradient energy is the Dirichlet form of
+ *     whichever stencil is in use;
  *   - the coefficient of the (a'/a)^2 f term in eq. (scalar-evo) is
  *     r(s - r + 2); the printed r(s - r - 2) does not follow from eq. (fe)
  *     under the rescaling of Sec. II.B (it would leave an (a'/a)^2 term in the
@@ -46,7 +48,7 @@ typedef struct {
     double L;        /* comoving box side, program units */
     double dt;       /* program time step */
     int32_t beta;    /* exponent of the dominant term c1 f^beta / beta */
-    int32_t pad_;
+    int32_t stencil; /* Laplacian: 7 (6 neighbours) or 27 (Sec. II.C) */
     double c1;       /* program-unit coupling of the dominant term */
     double G_re;     /* program-unit g^2 of the g^2 f1^2 f2^2 / 2 term */
     double r, s;     /* rescaling exponents, s - 2r + 3 = 0 */
@@ -103,6 +105,7 @@ int orc_abi(void) { return 1; }
 int orc_check_params(const orc_params *p)
 {
     if (p->N < 1 || p->L <= 0.0 || p->dt <= 0.0 || p->beta < 2) return 1;
+    if (p->stencil != 7 && p->stencil != 27) return 3;
     if (fabs(p->s - 2.0 * p->r + 3.0) > 1e-12) return 2;
     return 0;
 }
@@ -115,7 +118,7 @@ void orc_laplacian(const orc_params *p, const double *f, double *out)
     for (int64_t z = 0; z < N; ++z)
         for (int64_t y = 0; y < N; ++y)
             for (int64_t x = 0; x < N; ++x)
-                out[IDX(x, y, z, N)] = orc_lap_site(f, N, x, y, z, inv_dx2);
+                out[IDX(x, y, z, N)] = orc_lap_site(p, f, N, x, y, z, inv_dx2);
 }
 
 void orc_grad2(const orc_params *p, const double *f, double *out)
@@ -126,7 +129,7 @@ void orc_grad2(const orc_params *p, const double *f, double *out)
     for (int64_t z = 0; z < N; ++z)
         for (int64_t y = 0; y < N; ++y)
             for (int64_t x = 0; x < N; ++x)
-                out[IDX(x, y, z, N)] = orc_grad2_site(f, N, x, y, z, inv_dx2);
+                out[IDX(x, y, z, N)] = orc_grad2_site(p, f, N, x, y, z, inv_dx2);
 }
 
 /* out[0] = Sg, out[1] = SV at scale factor a (see orc_reduce in the core). */
@@ -189,7 +192,7 @@ double orc_init_physical(const orc_params *p, const double *f1, const double *f2
             for (int64_t x = 0; x < N; ++x) {
                 int64_t i = IDX(x, y, z, N);
                 kin += 0.5 * (v1[i] * v1[i] + v2[i] * v2[i]);
-                grad += orc_grad2_site(f1, N, x, y, z, inv_dx2) + orc_grad2_site(f2, N, x, y, z, inv_dx2);
+                grad += orc_grad2_site(p, f1, N, x, y, z, inv_dx2) + orc_grad2_site(p, f2, N, x, y, z, inv_dx2);
                 pot += orc_vpr(p, p->G_re, f1[i], f2[i], ap1, ap2);
             }
     double rho = (kin + 0.5 * pow(a0, -2.0 * s - 2.0) * grad + pot) / (double)N3;
@@ -231,7 +234,7 @@ void orc_rho_p(const orc_params *p, const double *f1, const double *f2, const do
                 int64_t i = IDX(x, y, z, N);
                 double q1 = v1[i] - r * hub * fs1[i], q2 = v2[i] - r * hub * fs2[i];
                 double K = 0.5 * (q1 * q1 + q2 * q2);
-                double G = gfac * (orc_grad2_site(fs1, N, x, y, z, inv_dx2) + orc_grad2_site(fs2, N, x, y, z, inv_dx2));
+                double G = gfac * (orc_grad2_site(p, fs1, N, x, y, z, inv_dx2) + orc_grad2_site(p, fs2, N, x, y, z, inv_dx2));
                 double V = orc_vpr(p, p->G_re, fs1[i], fs2[i], ap1, ap2);
                 double rr = K + G + V, pp = K - G / 3.0 - V;
                 if (rho) rho[i] = rr;
