@@ -31,7 +31,7 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, stencil: int):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     or None when it is missing or was taken on a different sweep source."""
     from paper_0911_5692_amd.profile_sweep import sweep_source_hash
@@ -41,7 +41,7 @@ def measured_traffic(workload: str):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("sweep_source_hash") != sweep_source_hash():
+    if d.get("sweep_source_hash") != sweep_source_hash(stencil):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -128,7 +128,7 @@ def main() -> int:
     sweep_ms = kms[1]
     alg_bytes = 8 * esize * w.sites  # read f, v; write v, f_new; two fields
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name)
+    traffic = measured_traffic(w.name, w.stencil)
     log(f"kernel ms: a-update {kms[0]:.4f}, sweep {sweep_ms:.4f}, reduce {kms[2]:.4f}; "
         f"sweep {achieved:.0f} GB/s")
     lat.close()
@@ -154,12 +154,16 @@ def main() -> int:
         "dtype": w.dtype,
         "data": "synthetic",
         "config": {"workload": f"{w.name}: m^2 phi^2 + g^2 phi^2 chi^2 (G=2.5e5), {w.N}^3 periodic, "
-                               f"L={w.L}, dt={w.dt}, vacuum fluctuations, seed [3,0,i,k]",
-                   "N": w.N, "sites": w.sites, "lattice_dtype": w.dtype, "launch_shape": shape,
+                               f"L={w.L}, dt={w.dt}, {w.stencil}-point Laplacian, vacuum fluctuations, "
+                               f"seed [3,0,i,k]",
+                   "N": w.N, "sites": w.sites, "lattice_dtype": w.dtype, "stencil": w.stencil,
+                   "launch_shape": shape,
                    "step_hbm_frac_algorithmic": round(value * 1e9 * 8 * esize / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_sweep (fused kick-drift)",
+                     "traffic": traffic,
+                     "kernel": "k_sweep_lds27 (fused kick-drift, 27-point)" if w.stencil == 27
+                     else "k_sweep_lds (fused kick-drift, 7-point)",
                      "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }

@@ -17,8 +17,18 @@
  *     p1 = -2s + (2-beta) r,  p2 = -2s - 2r,  with s - 2r + 3 = 0.
  *   lambda phi^4: beta = 4, r = 1, s = -1.   m^2 phi^2: beta = 2, r = 3/2, s = 0.
  *
- * The Laplacian is the 7-point (6-neighbour) stencil, periodic in x, y, z
- * (the LATTICEEASY discretisation named in Sec. II.C).
+ * Laplacian (periodic in x, y, z), chosen per context by lf_params.stencil:
+ *   7:  the 6-neighbour stencil of LATTICEEASY (named in Sec. II.C);
+ *   27: the stencil the paper itself uses (Sec. II.C): all 26 neighbours of
+ *       the 3x3x3 cube, second-order accurate and fourth-order isotropic,
+ *       weights (centre, face, edge, corner) = (-64/15, 7/15, 1/10, 1/30)/dx^2.
+ * The gradient energy <|grad f|^2> in eq. (scale) and in the energies is the
+ * Dirichlet form of the same stencil, -<f Lap f>: forward differences
+ * |d+ f|^2 for 7 points; for 27 points the sum over the 13 bonds b whose
+ * first nonzero component (in z, y, x order) is +1 of
+ * w_b (f(x+b) - f(x))^2 / dx^2 with w = 7/15 (face), 1/10 (edge),
+ * 1/30 (corner).  With it, the semi-discrete field equation conserves the
+ * discrete energy exactly.
  *
  * Layout.  Every lattice array is N^3 contiguous elements, x fastest:
  * element (x, y, z) sits at (z*N + y)*N + x.  Arrays are device pointers,
@@ -54,7 +64,7 @@
 extern "C" {
 #endif
 
-#define LF_ABI_VERSION 1
+#define LF_ABI_VERSION 2
 
 typedef enum lf_status {
     LF_OK = 0,
@@ -84,13 +94,13 @@ typedef struct lf_params {
     int32_t zchunk;   /* planes per z-chunk of the LDS sweep, 0 = automatic */
     int32_t tile_x;   /* sweep tile columns: 0 = automatic, 64 or 128 (128 with
                          tile_y 4 or 8 only) */
-    int32_t reserved; /* must be 0 */
+    int32_t stencil;  /* Laplacian: 0 or 7 = 7-point, 27 = 27-point (see above) */
 } lf_params;
 
 /* Volume averages at the synchronised time k (eq. rho-pres in program
  * units): f(k) = f(k+1/2) - dt/2 v(k), a_k = a_{k+1/2} - dt/2 a'_k,
  *   K_i  = < (v_i - r (a'/a) f_i)^2 / 2 >     kinetic
- *   Gr_i = < a^(-2s-2) |grad+ f_i|^2 / 2 >    gradient (forward differences)
+ *   Gr_i = < a^(-2s-2) |grad f_i|^2 / 2 >     gradient (the stencil's Dirichlet form)
  *   P    = < V_pr(f, a) >                      potential
  *   rho  = sum K + sum Gr + P
  *   R    = (kappa^2/3) a^(2-2r) rho / a'^2 - 1 Friedmann residual, the
@@ -111,7 +121,8 @@ typedef struct lf_scalars {
     double bg_f[2];     /* background f_bar_i(k+1/2) */
     double bg_v[2];     /* background v_bar_i(k) */
     double pend[4];     /* sums over the stored f(k+1/2) that the next step's
-                           a'' needs: sum|grad+ f1|^2 dx^2, same for f2,
+                           a'' needs: the gradient sums of f1 and f2 (dx^2
+                           |grad f|^2 summed; for 27 points times 30), then
                            sum f1^beta, sum f1^2 f2^2 */
     uint32_t status;
     uint32_t pad_;
@@ -155,7 +166,7 @@ int lf_init(lf_ctx *ctx, const void *f1, const void *f2, const void *v1, const v
 /* Initialise from fields and rescaled physical velocities
  * u_i = (A/B) a^(r-s) dphi_i/dt (Sec. II.B, conversion to program units):
  * a'_0 > 0 follows from the Friedmann constraint
- *   a'^2 = (kappa^2/3) a^(2-2r) < sum_i u_i^2/2 + a^(-2s-2)|grad+ f_i|^2/2 + V_pr >
+ *   a'^2 = (kappa^2/3) a^(2-2r) < sum_i u_i^2/2 + a^(-2s-2)|grad f_i|^2/2 + V_pr >
  * and v_i = u_i + r (a'_0/a_0) f_i.  Blocking (returns a'_0 in *ad0_out). */
 int lf_init_physical(lf_ctx *ctx, const void *f1, const void *f2, const void *u1,
                      const void *u2, int in_dtype, double a0, double *ad0_out);

@@ -30,7 +30,7 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("beta", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("c1", ctypes.c_double), ("G", ctypes.c_double), ("r", ctypes.c_double),
                 ("s", ctypes.c_double), ("kappa2", ctypes.c_double), ("tile_y", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("stencil", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

@@ -8,9 +8,11 @@
 //           stored fields (the global a'' coupling) and of the fields themselves;
 //   scalar  (k_adj_scalar): the chain through a'', the time-centred a' update,
 //           F_a and the a-powers of V_pr, in FP64, one thread;
-//   pass B  (k_adj_fields): the field cotangents: the 7-point Laplacian of
-//           mu = lambda_v' + dt lambda_f' (the stencil is symmetric), the local
-//           2x2 Hessian of V_pr, and the rank-one terms from Sg and SV.
+//   pass B  (k_adj_fields): the field cotangents: the Laplacian (7 or 27
+//           points) of mu = lambda_v' + dt lambda_f' (both stencils are
+//           symmetric), the local 2x2 Hessian of V_pr, and the rank-one terms
+//           from Sg and SV (the derivative of the gradient energy is -2 Lap f,
+//           since it is the Dirichlet form of the same Laplacian).
 // Cotangent arrays are FP64 whatever the state precision; stored states are
 // deviations from the FP64 background and are turned back into full fields
 // f = f_bar + d in FP64 on the fly.
@@ -66,27 +68,6 @@ __device__ inline double ipw(double x, int n)
     return r;
 }
 
-struct Nbr {
-    int64_t i, xm, xp, ym, yp, zm, zp;
-};
-
-__device__ inline Nbr nbr_of(int64_t i, int N)
-{
-    const int64_t NN = (int64_t)N * N;
-    const int x = (int)(i % N);
-    const int64_t t = i / N;
-    const int y = (int)(t % N), z = (int)(t / N);
-    Nbr n;
-    n.i = i;
-    n.xm = (x == 0) ? i + (N - 1) : i - 1;
-    n.xp = (x == N - 1) ? i - (N - 1) : i + 1;
-    n.ym = (y == 0) ? i + (int64_t)(N - 1) * N : i - N;
-    n.yp = (y == N - 1) ? i - (int64_t)(N - 1) * N : i + N;
-    n.zm = (z == 0) ? i + (int64_t)(N - 1) * NN : i - NN;
-    n.zp = (z == N - 1) ? i - (int64_t)(N - 1) * NN : i + NN;
-    return n;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------ loss seed
@@ -94,9 +75,9 @@ __device__ inline Nbr nbr_of(int64_t i, int N)
 // Cotangent of E = sum_i wK_i K_i + wG_i G_i at the synchronised time of
 // the state (d, e; background and scale factor in S), written to lam[0..3]
 // (lambda_f1, lambda_f2, lambda_v1, lambda_v2), plus the per-block sums the
-// scalar part needs: sum q1^2, sum q2^2, sum |d+ fs1|^2, sum |d+ fs2|^2 (raw),
+// scalar part needs: sum q1^2, sum q2^2, the raw gradient sums of fs1 and fs2,
 // sum_i wK_i q_i fs_i.
-template <typename T>
+template <typename T, int ST>
 __global__ void __launch_bounds__(256) k_adj_seed(const T *__restrict__ d1, const T *__restrict__ d2,
                                                   const T *__restrict__ e1, const T *__restrict__ e2,
                                                   int N, const DevParams *__restrict__ P,
@@ -105,7 +86,7 @@ __global__ void __launch_bounds__(256) k_adj_seed(const T *__restrict__ d1, cons
                                                   double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
-    const double h = 0.5 * P->dt, r = P->r, s = P->s, inv_dx2 = 1.0 / (P->dx * P->dx);
+    const double h = 0.5 * P->dt, r = P->r, s = P->s, inv_dx2 = P->gw / (P->dx * P->dx);
     const double a = S->a_half - h * S->ad, hub = S->ad / a;
     const double gfac = 0.5 * pow(a, -2.0 * s - 2.0);
     const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
@@ -114,15 +95,21 @@ __global__ void __launch_bounds__(256) k_adj_seed(const T *__restrict__ d1, cons
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const Nbr n = nbr_of(i, N);
-        auto sy1 = [&](int64_t j) { return (double)d1[j] - h * (double)e1[j]; };
-        auto sy2 = [&](int64_t j) { return (double)d2[j] - h * (double)e2[j]; };
-        const double c1v = sy1(i), c2v = sy2(i);
+        const Wrap wr(i, N);
+        auto sy1 = [&](int dx, int dy, int dz) {
+            const int64_t j = wr(dx, dy, dz);
+            return (double)d1[j] - h * (double)e1[j];
+        };
+        auto sy2 = [&](int dx, int dy, int dz) {
+            const int64_t j = wr(dx, dy, dz);
+            return (double)d2[j] - h * (double)e2[j];
+        };
+        const double c1v = (double)d1[i] - h * (double)e1[i], c2v = (double)d2[i] - h * (double)e2[i];
         const double fs1 = gs1 + c1v, fs2 = gs2 + c2v;
         const double q1 = (S->bg_v[0] + (double)e1[i]) - r * hub * fs1;
         const double q2 = (S->bg_v[1] + (double)e2[i]) - r * hub * fs2;
-        const double lap1 = (((sy1(n.xm) + sy1(n.xp)) + (sy1(n.ym) + sy1(n.yp))) + (sy1(n.zm) + sy1(n.zp)) - 6.0 * c1v) * inv_dx2;
-        const double lap2 = (((sy2(n.xm) + sy2(n.xp)) + (sy2(n.ym) + sy2(n.yp))) + (sy2(n.zm) + sy2(n.zp)) - 6.0 * c2v) * inv_dx2;
+        const double lap1 = lap_raw<ST, double>(sy1, c1v) * inv_dx2;
+        const double lap2 = lap_raw<ST, double>(sy2, c2v) * inv_dx2;
         const double dq1 = wK1 * q1 / n3, dq2 = wK2 * q2 / n3;
         const double dfs1 = -r * hub * dq1 - 2.0 * wG1 * gfac * lap1 / n3;
         const double dfs2 = -r * hub * dq2 - 2.0 * wG2 * gfac * lap2 / n3;
@@ -132,10 +119,8 @@ __global__ void __launch_bounds__(256) k_adj_seed(const T *__restrict__ d1, cons
         lv2[i] = dq2 - h * dfs2;
         acc[0] += q1 * q1;
         acc[1] += q2 * q2;
-        double t0 = sy1(n.xp) - c1v, t1 = sy1(n.yp) - c1v, t2 = sy1(n.zp) - c1v;
-        acc[2] += t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = sy2(n.xp) - c2v; t1 = sy2(n.yp) - c2v; t2 = sy2(n.zp) - c2v;
-        acc[3] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[2] += grad_raw<ST>(sy1, c1v);
+        acc[3] += grad_raw<ST>(sy2, c2v);
         acc[4] += wK1 * q1 * fs1 + wK2 * q2 * fs2;
     }
     bsum<5>(acc, part + (size_t)blockIdx.x * 5);
@@ -152,7 +137,7 @@ __global__ void __launch_bounds__(256) k_adj_seed_scalar(const double *part, int
     if (threadIdx.x != 0) return;
     const double h = 0.5 * P->dt, r = P->r, s = P->s, n3 = P->N3;
     const double a = S->a_half - h * S->ad, ad = S->ad;
-    const double gfac = 0.5 * pow(a, -2.0 * s - 2.0) / (P->dx * P->dx);
+    const double gfac = 0.5 * pow(a, -2.0 * s - 2.0) * P->gw / (P->dx * P->dx);
     const double K1 = 0.5 * t[0] / n3, K2 = 0.5 * t[1] / n3;
     const double G1 = gfac * t[2] / n3, G2 = gfac * t[3] / n3;
     const double E = w[0] * K1 + w[1] * K2 + w[2] * G1 + w[3] * G2;
@@ -169,10 +154,11 @@ __global__ void __launch_bounds__(256) k_adj_seed_scalar(const double *part, int
 
 // Pass A: sums over the stored fields f = f_bar + d at k+1/2 and
 // mu = lambda_v' + dt lambda_f' (cotangent of v(k+1)):
-//  0: sum mu_i S6(f_i)   1: sum mu_i f_i   2: sum mu1 f1 f2^2 + mu2 f1^2 f2
-//  3: sum mu1 f1^(beta-1)   4: sum f1^beta   5: sum f1^2 f2^2   6: sum |d+ f_i|^2
-// (S6: raw 6-neighbour sum minus 6 f; no 1/dx^2)
-template <typename T>
+//  0: sum mu_i S(f_i)   1: sum mu_i f_i   2: sum mu1 f1 f2^2 + mu2 f1^2 f2
+//  3: sum mu1 f1^(beta-1)   4: sum f1^beta   5: sum f1^2 f2^2
+//  6: raw gradient sums of f_1 plus f_2
+// (S: the raw stencil sum lap_raw<ST>; no 1/dx^2, no stencil weight)
+template <typename T, int ST>
 __global__ void __launch_bounds__(256) k_adj_reduce(const T *__restrict__ d1, const T *__restrict__ d2,
                                                     int N, int beta, const DevScalars *__restrict__ tape,
                                                     const double *__restrict__ lf1, const double *__restrict__ lf2,
@@ -184,13 +170,13 @@ __global__ void __launch_bounds__(256) k_adj_reduce(const T *__restrict__ d1, co
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const Nbr n = nbr_of(i, N);
+        const Wrap wr(i, N);
+        auto v1 = [&](int dx, int dy, int dz) { return (double)d1[wr(dx, dy, dz)]; };
+        auto v2 = [&](int dx, int dy, int dz) { return (double)d2[wr(dx, dy, dz)]; };
         const double a1 = (double)d1[i], a2 = (double)d2[i];
         const double f1 = g1 + a1, f2 = g2 + a2;
-        const double s1 = ((((double)d1[n.xm] + (double)d1[n.xp]) + ((double)d1[n.ym] + (double)d1[n.yp]))
-                           + ((double)d1[n.zm] + (double)d1[n.zp])) - 6.0 * a1;
-        const double s2 = ((((double)d2[n.xm] + (double)d2[n.xp]) + ((double)d2[n.ym] + (double)d2[n.yp]))
-                           + ((double)d2[n.zm] + (double)d2[n.zp])) - 6.0 * a2;
+        const double s1 = lap_raw<ST, double>(v1, a1);
+        const double s2 = lap_raw<ST, double>(v2, a2);
         const double mu1 = lv1[i] + dt * lf1[i], mu2 = lv2[i] + dt * lf2[i];
         acc[0] += mu1 * s1 + mu2 * s2;
         acc[1] += mu1 * f1 + mu2 * f2;
@@ -198,16 +184,13 @@ __global__ void __launch_bounds__(256) k_adj_reduce(const T *__restrict__ d1, co
         acc[3] += mu1 * ipw(f1, beta - 1);
         acc[4] += ipw(f1, beta);
         acc[5] += f1 * f1 * f2 * f2;
-        double t0 = (double)d1[n.xp] - a1, t1 = (double)d1[n.yp] - a1, t2 = (double)d1[n.zp] - a1;
-        double gsum = t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = (double)d2[n.xp] - a2; t1 = (double)d2[n.yp] - a2; t2 = (double)d2[n.zp] - a2;
-        acc[6] += gsum + t0 * t0 + t1 * t1 + t2 * t2;
+        acc[6] += grad_raw<ST>(v1, a1) + grad_raw<ST>(v2, a2);
     }
     bsum<7>(acc, part + (size_t)blockIdx.x * 7);
 }
 
 // Scalar chain of one reverse step.  A: [la, lw, gG, E]; writes the field
-// coefficients to cf: [dt a^(-2s-2)/dx^2, dt bcoef, c1 a^p1, G a^p2, cSg, cSV, dt].
+// coefficients to cf: [dt a^(-2s-2) gw/dx^2, dt bcoef, c1 a^p1, G a^p2, cSg, cSV, dt].
 __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk,
                                                     const DevParams *__restrict__ P,
                                                     const DevScalars *__restrict__ tape, double *A,
@@ -223,7 +206,8 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     const double ap1 = pow(a, p1), ap2 = pow(a, p2);
     const double dap1 = p1 * pow(a, p1 - 1.0), dap2 = p2 * pow(a, p2 - 1.0);
     // forward scalars of this step
-    const double Sg = R[6] / (dx * dx * n3);
+    const double gw = P->gw;
+    const double Sg = gw * R[6] / (dx * dx * n3);
     const double SV = (c1 * ap1 * R[4] / (double)beta + 0.5 * G * ap2 * R[5]) / n3;
     const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
     const double c = (-s - 2.0) * dt / (4.0 * a);
@@ -234,7 +218,7 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     const double rr = r * (s - r + 2.0);
     const double bc = rr * (adh / a) * (adh / a) + r * add / a;
     // kick sensitivities
-    const double galpha = dt * R[0] / (dx * dx);
+    const double galpha = dt * gw * R[0] / (dx * dx);
     const double gbeta = dt * R[1];
     const double gGk = -dt * ap2 * R[2];
     const double gak = -dt * (c1 * dap1 * R[3] + G * dap2 * R[2]);
@@ -261,17 +245,17 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     A[0] = ga;
     A[1] = g_w;
     A[2] += gGk + gSV * sdVdG / n3;
-    cf[0] = dt * alpha / (dx * dx);
+    cf[0] = dt * alpha * gw / (dx * dx);
     cf[1] = dt * bc;
     cf[2] = c1 * ap1;
     cf[3] = G * ap2;
-    cf[4] = -2.0 * gSg / (n3 * dx * dx);  // multiplies the raw 6-neighbour sum of f
+    cf[4] = -2.0 * gSg * gw / (n3 * dx * dx);  // multiplies the raw stencil sum of f
     cf[5] = gSV / n3;
     cf[6] = dt;
 }
 
 // Pass B: field cotangents of X_k from those of X_{k+1} (in -> out).
-template <typename T>
+template <typename T, int ST>
 __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, const T *__restrict__ d2,
                                                     int N, int beta, const DevScalars *__restrict__ tape,
                                                     const double *__restrict__ cf,
@@ -284,17 +268,23 @@ __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, co
     const double cl = cf[0], cb = cf[1], c1a = cf[2], Ga = cf[3], cSg = cf[4], cSV = cf[5], dt = cf[6];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const Nbr n = nbr_of(i, N);
-        auto mu1 = [&](int64_t j) { return lv1[j] + dt * lf1[j]; };
-        auto mu2 = [&](int64_t j) { return lv2[j] + dt * lf2[j]; };
-        const double m1 = mu1(i), m2 = mu2(i);
-        const double lm1 = (((mu1(n.xm) + mu1(n.xp)) + (mu1(n.ym) + mu1(n.yp))) + (mu1(n.zm) + mu1(n.zp))) - 6.0 * m1;
-        const double lm2 = (((mu2(n.xm) + mu2(n.xp)) + (mu2(n.ym) + mu2(n.yp))) + (mu2(n.zm) + mu2(n.zp))) - 6.0 * m2;
+        const Wrap wr(i, N);
+        auto mu1 = [&](int dx, int dy, int dz) {
+            const int64_t j = wr(dx, dy, dz);
+            return lv1[j] + dt * lf1[j];
+        };
+        auto mu2 = [&](int dx, int dy, int dz) {
+            const int64_t j = wr(dx, dy, dz);
+            return lv2[j] + dt * lf2[j];
+        };
+        auto v1 = [&](int dx, int dy, int dz) { return (double)d1[wr(dx, dy, dz)]; };
+        auto v2 = [&](int dx, int dy, int dz) { return (double)d2[wr(dx, dy, dz)]; };
+        const double m1 = lv1[i] + dt * lf1[i], m2 = lv2[i] + dt * lf2[i];
+        const double lm1 = lap_raw<ST, double>(mu1, m1);
+        const double lm2 = lap_raw<ST, double>(mu2, m2);
         const double a1 = (double)d1[i], a2 = (double)d2[i];
-        const double s1 = ((((double)d1[n.xm] + (double)d1[n.xp]) + ((double)d1[n.ym] + (double)d1[n.yp]))
-                           + ((double)d1[n.zm] + (double)d1[n.zp])) - 6.0 * a1;
-        const double s2 = ((((double)d2[n.xm] + (double)d2[n.xp]) + ((double)d2[n.ym] + (double)d2[n.yp]))
-                           + ((double)d2[n.zm] + (double)d2[n.zp])) - 6.0 * a2;
+        const double s1 = lap_raw<ST, double>(v1, a1);
+        const double s2 = lap_raw<ST, double>(v2, a2);
         const double f1 = g1 + a1, f2 = g2 + a2;
         const double h11 = c1a * (double)(beta - 1) * ipw(f1, beta - 2) + Ga * f2 * f2;
         const double h12 = 2.0 * Ga * f1 * f2;
@@ -323,42 +313,53 @@ __global__ void __launch_bounds__(256) k_adj_desync(int64_t N3, double h, const 
 
 // ------------------------------------------------------------ launchers
 
-void launch_adj_seed(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
-                     const double *w, double *const lam[4], double *part, int nblk, double *A,
-                     hipStream_t st)
+template <typename T, int ST>
+static void adj_seed_t(const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
+                       const double *w, double *const lam[4], double *part, int nblk, hipStream_t st)
 {
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_adj_seed<float>, dim3(nblk), dim3(256), 0, st, (const float *)s4[0],
-                           (const float *)s4[1], (const float *)s4[2], (const float *)s4[3], N, P, S, w,
-                           lam[0], lam[1], lam[2], lam[3], part);
-    else
-        hipLaunchKernelGGL(k_adj_seed<double>, dim3(nblk), dim3(256), 0, st, (const double *)s4[0],
-                           (const double *)s4[1], (const double *)s4[2], (const double *)s4[3], N, P, S, w,
-                           lam[0], lam[1], lam[2], lam[3], part);
+    hipLaunchKernelGGL((k_adj_seed<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0], (const T *)s4[1],
+                       (const T *)s4[2], (const T *)s4[3], N, P, S, w, lam[0], lam[1], lam[2], lam[3], part);
+}
+
+void launch_adj_seed(int stencil, int dtype, const void *const s4[4], int N, const DevParams *P,
+                     const DevScalars *S, const double *w, double *const lam[4], double *part, int nblk,
+                     double *A, hipStream_t st)
+{
+    if (stencil == 27) {
+        if (dtype == 0) adj_seed_t<float, 27>(s4, N, P, S, w, lam, part, nblk, st);
+        else adj_seed_t<double, 27>(s4, N, P, S, w, lam, part, nblk, st);
+    } else {
+        if (dtype == 0) adj_seed_t<float, 7>(s4, N, P, S, w, lam, part, nblk, st);
+        else adj_seed_t<double, 7>(s4, N, P, S, w, lam, part, nblk, st);
+    }
     hipLaunchKernelGGL(k_adj_seed_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, S, w, A);
 }
 
-void launch_adj_step(int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
-                     const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
-                     double *part, int nblk, double *A, double *cf, hipStream_t st)
+template <typename T, int ST>
+static void adj_step_t(const void *d1, const void *d2, int N, int beta, const DevParams *P,
+                       const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
+                       double *part, int nblk, double *A, double *cf, int gridB, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_adj_reduce<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)d1, (const T *)d2, N,
+                       beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
+    hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
+    hipLaunchKernelGGL((k_adj_fields<T, ST>), dim3(gridB), dim3(256), 0, st, (const T *)d1, (const T *)d2, N,
+                       beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0], lout[1], lout[2], lout[3]);
+}
+
+void launch_adj_step(int stencil, int dtype, const void *d1, const void *d2, int N, int beta,
+                     const DevParams *P, const DevScalars *tape, double dt, double *const lin[4],
+                     double *const lout[4], double *part, int nblk, double *A, double *cf, hipStream_t st)
 {
     const int64_t N3 = (int64_t)N * N * N;
     int64_t g = (N3 + 255) / 256;
     const int gridB = (int)(g > 65536 ? 65536 : g);
-    if (dtype == 0) {
-        hipLaunchKernelGGL(k_adj_reduce<float>, dim3(nblk), dim3(256), 0, st, (const float *)d1,
-                           (const float *)d2, N, beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
-        hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
-        hipLaunchKernelGGL(k_adj_fields<float>, dim3(gridB), dim3(256), 0, st, (const float *)d1,
-                           (const float *)d2, N, beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0],
-                           lout[1], lout[2], lout[3]);
+    if (stencil == 27) {
+        if (dtype == 0) adj_step_t<float, 27>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
+        else adj_step_t<double, 27>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
     } else {
-        hipLaunchKernelGGL(k_adj_reduce<double>, dim3(nblk), dim3(256), 0, st, (const double *)d1,
-                           (const double *)d2, N, beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
-        hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
-        hipLaunchKernelGGL(k_adj_fields<double>, dim3(gridB), dim3(256), 0, st, (const double *)d1,
-                           (const double *)d2, N, beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0],
-                           lout[1], lout[2], lout[3]);
+        if (dtype == 0) adj_step_t<float, 7>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
+        else adj_step_t<double, 7>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
     }
 }
 

@@ -51,13 +51,16 @@ struct Shape {
 // resident count is only queried on a machine with a GPU; elsewhere (and for
 // the workspace size) 3 blocks on 256 CUs is assumed, which only changes the
 // partial-sum row count.
+// 7 or 27 (lf_params.stencil 0 means 7).
+int stencil_of(const lf_params *p) { return p->stencil == 27 ? 27 : 7; }
+
 int resident_blocks(const lf_params *p, int tile_x, int tile_y)
 {
     int dev = 0, cus = 0;
     int per_cu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        per_cu = sweep_lds_blocks_per_cu(p->dtype, tile_x, tile_y, p->beta);
+        per_cu = sweep_lds_blocks_per_cu(stencil_of(p), p->dtype, tile_x, tile_y, p->beta);
     (void)hipGetLastError();
     if (per_cu <= 0 || cus <= 0) return 3 * 256;
     return per_cu * cus;
@@ -71,7 +74,8 @@ Shape shape_of(const lf_params *p)
         sh.tile_y = p->tile_y;
         sh.tile_x = p->tile_x ? p->tile_x : 64;
     } else if (N >= 256) {
-        sh.tile_x = 128;
+        // the 27-point FP64 sweep holds 3 blocks per CU only with 64-wide tiles
+        sh.tile_x = (stencil_of(p) == 27 && p->dtype == LF_F64) ? 64 : 128;
         sh.tile_y = 8;
     } else {
         sh.tile_x = 64;
@@ -150,7 +154,8 @@ int validate(const lf_params *p)
         return fail(LF_EINVAL, "tile_x=%d: must be 0 (auto), 64 or 128", p->tile_x);
     if (p->tile_x == 128 && p->tile_y != 4 && p->tile_y != 8)
         return fail(LF_EINVAL, "tile_x=128 needs tile_y 4 or 8");
-    if (p->reserved != 0) return fail(LF_EINVAL, "reserved must be 0");
+    if (p->stencil != 0 && p->stencil != 7 && p->stencil != 27)
+        return fail(LF_EINVAL, "stencil=%d: must be 0 or 7 (7-point) or 27 (27-point)", p->stencil);
     return LF_OK;
 }
 
@@ -196,11 +201,12 @@ void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
     launch_aupdate(c->part, c->sh.rows, c->P, c->S, c->C, st);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (c->sh.tile_y == 1) {
-        launch_sweep_plain(c->p.dtype, c->p.beta, in, out, c->p.N, c->C, st);
+        launch_sweep_plain(stencil_of(&c->p), c->p.dtype, c->p.beta, in, out, c->p.N, c->C, st);
         if (ev) (void)hipEventRecord(ev[2], st);
-        launch_reduce(c->p.dtype, out[0], out[1], c->p.N, c->S->bg_f, c->p.beta, c->part, c->sh.rows, st);
+        launch_reduce(stencil_of(&c->p), c->p.dtype, out[0], out[1], c->p.N, c->S->bg_f, c->p.beta, c->part,
+                      c->sh.rows, st);
     } else {
-        launch_sweep_lds(c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, in, out, c->p.N,
+        launch_sweep_lds(stencil_of(&c->p), c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, in, out, c->p.N,
                          c->sh.zchunk, c->C, c->part, st);
         if (ev) (void)hipEventRecord(ev[2], st);
     }
@@ -252,6 +258,9 @@ void fill_dev_params(const lf_params *p, DevParams *d)
     d->N = p->N;
     d->beta = p->beta;
     d->N3 = (double)p->N * p->N * p->N;
+    d->stencil = stencil_of(p);
+    d->gw = d->stencil == 27 ? 1.0 / 30.0 : 1.0;
+    d->pad = 0;
 }
 
 int check_ptr(const void *ptr, const char *name)
@@ -345,11 +354,11 @@ static int init_common(lf_ctx *c, const void *f1, const void *f2, const void *v1
     if (!(a0 > 0.0) || !isfinite(a0)) return fail(LF_EINVAL, "a0 must be finite and > 0");
     if (!isfinite(ad0)) return fail(LF_EINVAL, "ad0 must be finite");
     const int N = c->p.N;
-    launch_input_moments(in_dtype, f1, f2, v1, v2, N, c->p.beta, c->mom, kRedBlocks, c->stream);
+    launch_input_moments(stencil_of(&c->p), in_dtype, f1, f2, v1, v2, N, c->p.beta, c->mom, kRedBlocks, c->stream);
     launch_init_scalars(c->mom, kRedBlocks, c->P, c->S, physical, a0, ad0, c->stream);
     launch_init_fields(c->p.dtype, in_dtype, f1, f2, v1, v2, c->buf[0][0], c->buf[0][1],
                        c->buf[0][2], c->buf[0][3], N, c->P, c->S, c->stream);
-    launch_reduce(c->p.dtype, c->buf[0][0], c->buf[0][1], N, c->S->bg_f, c->p.beta, c->part,
+    launch_reduce(stencil_of(&c->p), c->p.dtype, c->buf[0][0], c->buf[0][1], N, c->S->bg_f, c->p.beta, c->part,
                   c->sh.rows, c->stream);
     HIPCHK(hipGetLastError());
     c->cur = 0;
@@ -424,7 +433,7 @@ int lf_energies(lf_ctx *c, lf_report *out)
     if (!c || !out) return fail(LF_EINVAL, "NULL argument");
     if (!c->inited) return fail(LF_ESTATE, "lf_energies before lf_init");
     const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
-    launch_energy(c->p.dtype, s4, c->p.N, c->P, c->S, c->enp, kRedBlocks, c->enout, c->stream);
+    launch_energy(stencil_of(&c->p), c->p.dtype, s4, c->p.N, c->P, c->S, c->enp, kRedBlocks, c->enout, c->stream);
     HIPCHK(hipGetLastError());
     double h[12];
     HIPCHK(hipMemcpyAsync(h, c->enout, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -455,7 +464,7 @@ int lf_rho_p(lf_ctx *c, void *rho, void *p, int out_dtype, double *avg)
         return fail(LF_EINVAL, "output arrays must be 256-byte aligned");
     const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
     // the energy partial rows (kRedBlocks x kNEn doubles) hold the 2 sums here
-    launch_rho_p(c->p.dtype, out_dtype, s4, rho, p, c->p.N, c->P, c->S, c->enp, kRedBlocks, c->enout, c->stream);
+    launch_rho_p(stencil_of(&c->p), c->p.dtype, out_dtype, s4, rho, p, c->p.N, c->P, c->S, c->enp, kRedBlocks, c->enout, c->stream);
     HIPCHK(hipGetLastError());
     double h[3];
     HIPCHK(hipMemcpyAsync(h, c->enout, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -710,7 +719,7 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
     HIPCHK(hipMemcpyAsync(wd, hw, sizeof hw, hipMemcpyHostToDevice, c->stream));
     // seed: cotangent of the final state
     const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
-    launch_adj_seed(c->p.dtype, s4, c->p.N, c->P, c->S, wd, lam[0], part, kRedBlocks, A, c->stream);
+    launch_adj_seed(stencil_of(&c->p), c->p.dtype, s4, c->p.N, c->P, c->S, wd, lam[0], part, kRedBlocks, A, c->stream);
     HIPCHK(hipGetLastError());
     int li = 0;
     const size_t bytes = n3 * esize(c->p.dtype);
@@ -728,7 +737,7 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
         }
         for (int64_t j = m - 1; j >= 0; --j) {
             const char *src = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
-            launch_adj_step(c->p.dtype, src, src + L.arr_bytes, c->p.N, c->p.beta, c->P, tape + j, c->p.dt,
+            launch_adj_step(stencil_of(&c->p), c->p.dtype, src, src + L.arr_bytes, c->p.N, c->p.beta, c->P, tape + j, c->p.dt,
                             lam[li], lam[li ^ 1], part, kRedBlocks, A, cf, c->stream);
             li ^= 1;
         }
@@ -756,7 +765,7 @@ namespace {
 
 struct TuneKey {
     char arch[64];
-    int N, dtype, beta;
+    int N, dtype, beta, stencil;
 };
 
 int current_arch(char *arch, size_t n)
@@ -774,7 +783,8 @@ int current_arch(char *arch, size_t n)
 }
 
 // Cache: one JSON object per line,
-// {"arch": "gfx950", "N": 512, "dtype": 0, "beta": 2, "tile_x": 128, "tile_y": 8, "zchunk": 256, "ms": 0.87}
+// {"arch": "gfx950", "N": 512, "dtype": 0, "beta": 2, "stencil": 7, "tile_x": 128, "tile_y": 8,
+//  "zchunk": 256, "ms": 0.87}
 int cache_lookup(const char *path, const TuneKey &k, lf_params *best)
 {
     if (!path) return 0;
@@ -784,11 +794,12 @@ int cache_lookup(const char *path, const TuneKey &k, lf_params *best)
     int found = 0;
     while (fgets(line, sizeof line, f)) {
         char arch[64] = {0};
-        int N, dt, beta, tx, ty, zc;
+        int N, dt, beta, st, tx, ty, zc;
         double ms;
-        if (sscanf(line, " {\"arch\": \"%63[^\"]\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"tile_x\": %d, "
-                         "\"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf", arch, &N, &dt, &beta, &tx, &ty, &zc, &ms) == 8 &&
-            !strcmp(arch, k.arch) && N == k.N && dt == k.dtype && beta == k.beta) {
+        if (sscanf(line, " {\"arch\": \"%63[^\"]\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"stencil\": %d, "
+                         "\"tile_x\": %d, \"tile_y\": %d, \"zchunk\": %d, \"ms\": %lf",
+                   arch, &N, &dt, &beta, &st, &tx, &ty, &zc, &ms) == 9 &&
+            !strcmp(arch, k.arch) && N == k.N && dt == k.dtype && beta == k.beta && st == k.stencil) {
             best->tile_x = tx;
             best->tile_y = ty;
             best->zchunk = zc;
@@ -804,8 +815,9 @@ void cache_append(const char *path, const TuneKey &k, const lf_params *b, double
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "{\"arch\": \"%s\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"tile_x\": %d, \"tile_y\": %d, "
-               "\"zchunk\": %d, \"ms\": %.6f}\n", k.arch, k.N, k.dtype, k.beta, b->tile_x, b->tile_y, b->zchunk, ms);
+    fprintf(f, "{\"arch\": \"%s\", \"N\": %d, \"dtype\": %d, \"beta\": %d, \"stencil\": %d, \"tile_x\": %d, "
+               "\"tile_y\": %d, \"zchunk\": %d, \"ms\": %.6f}\n",
+            k.arch, k.N, k.dtype, k.beta, k.stencil, b->tile_x, b->tile_y, b->zchunk, ms);
     fclose(f);
 }
 
@@ -870,6 +882,7 @@ int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_byt
     k.N = p->N;
     k.dtype = p->dtype;
     k.beta = p->beta;
+    k.stencil = stencil_of(p);
     *best = *p;
     if (cache_lookup(cache_path, k, best)) {
         if (best_ms) *best_ms = -1.0;
@@ -889,7 +902,8 @@ int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_byt
         if ((rc = lf_create(&cand[i], stream, workspace, ws_bytes, &c))) return rc;
         void *s4[4] = {c->buf[0][0], c->buf[0][1], c->buf[0][2], c->buf[0][3]};
         launch_fill_synthetic(c->p.dtype, s4, c->p.N, c->S, c->stream);
-        launch_reduce(c->p.dtype, s4[0], s4[1], c->p.N, c->S->bg_f, c->p.beta, c->part, c->sh.rows, c->stream);
+        launch_reduce(stencil_of(&c->p), c->p.dtype, s4[0], s4[1], c->p.N, c->S->bg_f, c->p.beta, c->part,
+                      c->sh.rows, c->stream);
         c->inited = 1;
         c->cur = 0;
         double ms = 0.0;
@@ -916,7 +930,7 @@ int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_byt
 
 struct lf_ens {
     int R;
-    int dtype, beta, tile_x, tile_y;
+    int dtype, beta, stencil, tile_x, tile_y;
     hipStream_t stream, cap;
     lf_ctx **sub;        // one context per realization, on slices of the workspace
     EnsEntry *tab;       // device table (workspace)
@@ -957,8 +971,9 @@ int ens_validate(int R, const lf_params *per)
     for (int r = 0; r < R; ++r) {
         int rc = validate(&per[r]);
         if (rc) return rc;
-        if (per[r].dtype != per[0].dtype || per[r].beta != per[0].beta)
-            return fail(LF_EINVAL, "realization %d: dtype and beta must match realization 0", r);
+        if (per[r].dtype != per[0].dtype || per[r].beta != per[0].beta ||
+            stencil_of(&per[r]) != stencil_of(&per[0]))
+            return fail(LF_EINVAL, "realization %d: dtype, beta and stencil must match realization 0", r);
         if (per[r].tile_y == 1) return fail(LF_EINVAL, "the ensemble needs an LDS sweep tile (tile_y != 1)");
     }
     const int ty = ens_tile_y(&per[0]), tx = ens_tile_x(&per[0]);
@@ -1033,6 +1048,7 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     e->R = R;
     e->dtype = per[0].dtype;
     e->beta = per[0].beta;
+    e->stencil = stencil_of(&per[0]);
     e->tile_x = ens_tile_x(&per[0]);
     e->tile_y = ens_tile_y(&per[0]);
     e->stream = (hipStream_t)stream;
@@ -1098,7 +1114,7 @@ namespace {
 void ens_enqueue_step(lf_ens *e, int parity, hipStream_t st)
 {
     launch_aupdate_ens(e->tab, e->R, st);
-    launch_sweep_ens(e->dtype, e->tile_x, e->tile_y, e->beta, e->tab, e->items, e->nitems, e->grid,
+    launch_sweep_ens(e->stencil, e->dtype, e->tile_x, e->tile_y, e->beta, e->tab, e->items, e->nitems, e->grid,
                      parity, st);
 }
 

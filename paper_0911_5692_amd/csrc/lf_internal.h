@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lf_stencil.h"
+
 namespace lf {
 
 constexpr int kMaxBeta = 6;
@@ -19,6 +21,9 @@ struct DevParams {
     double p1, p2;      // powers of a of the degree-beta and degree-4 terms of V_pr
     int N, beta;
     double N3;          // N^3 as a double
+    double gw;          // stencil weight: 1 (7-point) or 1/30 (27-point); multiplies
+                        // every raw Laplacian and gradient sum with 1/dx^2
+    int stencil, pad;   // 7 or 27
 };
 
 // FP64 scalar state of the evolution (device resident).
@@ -39,7 +44,7 @@ struct DevScalars {
 // kernel in both precisions (the sweep reads its own).
 template <typename T>
 struct Coef {
-    T Cl;        // dt a^(-2s-2) / dx^2  (multiplies the raw 6-neighbour sum)
+    T Cl;        // dt a^(-2s-2) gw / dx^2  (multiplies the raw stencil sum)
     T Cf;        // dt [r(s-r+2)(a'/a)^2 + r a''/a]
     T dt;
     T C2;        // dt G a^p2
@@ -68,32 +73,40 @@ struct EnsEntry {
 };
 
 // Launch helpers (lf_kernels.hip, lf_sweep.hip).  All enqueue on `st`.
-void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
+void launch_input_moments(int stencil, int in_dtype, const void *f1, const void *f2, const void *v1,
                           const void *v2, int N, int beta, double *part, int nblk, hipStream_t st);
 void launch_init_scalars(const double *part, int nblk, const DevParams *P, DevScalars *S,
                          int physical, double a0, double ad0, hipStream_t st);
 void launch_init_fields(int dtype, int in_dtype, const void *f1, const void *f2, const void *v1,
                         const void *v2, void *d1, void *d2, void *e1, void *e2, int N,
                         const DevParams *P, const DevScalars *S, hipStream_t st);
-void launch_reduce(int dtype, const void *d1, const void *d2, int N, const double *bg_f,
+void launch_reduce(int stencil, int dtype, const void *d1, const void *d2, int N, const double *bg_f,
                    int beta, double *part, int nblk, hipStream_t st);
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S,
                     CoefPair *C, hipStream_t st);
 void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st);
-void launch_sweep_ens(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
+void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
                       const int4 *items, int nitems, int grid, int parity, hipStream_t st);
-void launch_sweep_plain(int dtype, int beta, const void *const in[4], void *const out[4], int N,
+void launch_sweep_plain(int stencil, int dtype, int beta, const void *const in[4], void *const out[4], int N,
                         const CoefPair *C, hipStream_t st);
-void launch_sweep_lds(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+void launch_sweep_lds(int stencil, int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
                       void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
                       hipStream_t st);
 int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk);
+// 27-point LDS sweep (lf_sweep27.hip); launch_sweep_lds / launch_sweep_ens /
+// sweep_lds_blocks_per_cu dispatch to these for stencil 27.
+void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+                        void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
+                        hipStream_t st);
+void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
+                        const int4 *items, int nitems, int grid, int parity, hipStream_t st);
+int sweep_lds27_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);
 // Resident blocks per CU of the LDS sweep instantiation (0 if unknown, e.g.
 // no device).
-int sweep_lds_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);
-void launch_energy(int dtype, const void *const st4[4], int N, const DevParams *P,
+int sweep_lds_blocks_per_cu(int stencil, int dtype, int tile_x, int tile_y, int beta);
+void launch_energy(int stencil, int dtype, const void *const st4[4], int N, const DevParams *P,
                    const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st);
-void launch_rho_p(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
                   const DevParams *P, const DevScalars *S, double *part, int nblk, double *out_dev,
                   hipStream_t st);
 void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],
@@ -103,10 +116,10 @@ void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipS
 void launch_fill_synthetic(int dtype, void *const s4[4], int N, DevScalars *S, hipStream_t st);
 // adjoint (lf_adjoint.hip)
 constexpr int kNAdjPart = 7;
-void launch_adj_seed(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
+void launch_adj_seed(int stencil, int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
                      const double *w, double *const lam[4], double *part, int nblk, double *A,
                      hipStream_t st);
-void launch_adj_step(int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
+void launch_adj_step(int stencil, int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
                      const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
                      double *part, int nblk, double *A, double *cf, hipStream_t st);
 void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStream_t st);

@@ -66,44 +66,30 @@ __device__ inline double ipow_d(double x, int n)
     return r;
 }
 
-__device__ inline void site_xyz(int64_t i, int N, int &x, int &y, int &z)
-{
-    x = (int)(i % N);
-    int64_t t = i / N;
-    y = (int)(t % N);
-    z = (int)(t / N);
-}
-
 // ---------------------------------------------------------------- init
 
 // Moments of an input state (element type Tin), FP64 per site:
-//  0,1: sum f_i   2,3: sum u_i   4,5: sum u_i^2   6,7: sum |d+ f_i|^2 (no 1/dx^2)
+//  0,1: sum f_i   2,3: sum u_i   4,5: sum u_i^2
+//  6,7: raw gradient sum of f_i (grad_raw<ST>: no 1/dx^2, no stencil weight)
 //  8: sum f1^beta   9: sum f1^2 f2^2
-template <typename Tin>
+template <typename Tin, int ST>
 __global__ void __launch_bounds__(256) k_input_moments(const Tin *__restrict__ f1, const Tin *__restrict__ f2,
                                                        const Tin *__restrict__ u1, const Tin *__restrict__ u2,
                                                        int N, int beta, double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N;
     double acc[kNMom];
 #pragma unroll
     for (int i = 0; i < kNMom; ++i) acc[i] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int x, y, z;
-        site_xyz(i, N, x, y, z);
-        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
-        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
-        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const Wrap w(i, N);
         const double a = (double)f1[i], b = (double)f2[i];
         const double p = (double)u1[i], q = (double)u2[i];
         acc[0] += a; acc[1] += b; acc[2] += p; acc[3] += q;
         acc[4] += p * p; acc[5] += q * q;
-        double t0 = (double)f1[ix] - a, t1 = (double)f1[iy] - a, t2 = (double)f1[iz] - a;
-        acc[6] += t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = (double)f2[ix] - b; t1 = (double)f2[iy] - b; t2 = (double)f2[iz] - b;
-        acc[7] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[6] += grad_raw<ST>([&](int dx, int dy, int dz) { return (double)f1[w(dx, dy, dz)]; }, a);
+        acc[7] += grad_raw<ST>([&](int dx, int dy, int dz) { return (double)f2[w(dx, dy, dz)]; }, b);
         acc[8] += ipow_d(a, beta);
         acc[9] += a * a * b * b;
     }
@@ -128,7 +114,7 @@ __global__ void __launch_bounds__(kStage2Threads) k_init_scalars(const double *p
     if (physical) {
         // a'^2 = (kappa^2/3) a^(2-2r) rho_pr with physical velocities u
         const double rho = (0.5 * (m[4] + m[5])
-                            + 0.5 * pow(a0, -2.0 * s - 2.0) * (m[6] + m[7]) / (P->dx * P->dx)
+                            + 0.5 * pow(a0, -2.0 * s - 2.0) * P->gw * (m[6] + m[7]) / (P->dx * P->dx)
                             + P->c1 * pow(a0, P->p1) * m[8] / (double)P->beta
                             + 0.5 * P->G * pow(a0, P->p2) * m[9]) / N3;
         const double q = (P->kappa2 / 3.0) * pow(a0, 2.0 - 2.0 * r) * rho;
@@ -179,28 +165,21 @@ __global__ void __launch_bounds__(256) k_init_fields(const Tin *__restrict__ f1,
 // ---------------------------------------------------------------- reductions
 
 // Sums over the stored fields that the next scale-factor update needs
-// (eq. scale): sum |d+ f_i|^2 (raw differences, no 1/dx^2), sum f1^beta and
+// (eq. scale): the raw gradient sums of f_i (grad_raw<ST>), sum f1^beta and
 // sum f1^2 f2^2 with f = f_bar + d evaluated in FP64.
-template <typename T>
+template <typename T, int ST>
 __global__ void __launch_bounds__(256) k_reduce(const T *__restrict__ d1, const T *__restrict__ d2, int N,
                                                 const double *__restrict__ bg_f, int beta, double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N;
     const double g1 = bg_f[0], g2 = bg_f[1];
     double acc[kNPart] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int x, y, z;
-        site_xyz(i, N, x, y, z);
-        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
-        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
-        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const Wrap w(i, N);
         const double a = (double)d1[i], b = (double)d2[i];
-        double t0 = (double)d1[ix] - a, t1 = (double)d1[iy] - a, t2 = (double)d1[iz] - a;
-        acc[0] += t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = (double)d2[ix] - b; t1 = (double)d2[iy] - b; t2 = (double)d2[iz] - b;
-        acc[1] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[0] += grad_raw<ST>([&](int dx, int dy, int dz) { return (double)d1[w(dx, dy, dz)]; }, a);
+        acc[1] += grad_raw<ST>([&](int dx, int dy, int dz) { return (double)d2[w(dx, dy, dz)]; }, b);
         const double x1 = g1 + a, x2 = g2 + b;
         acc[2] += ipow_d(x1, beta);
         acc[3] += x1 * x1 * x2 * x2;
@@ -255,7 +234,7 @@ __device__ void aupdate_block(const double *part, int nblk, const DevParams *__r
     const int beta = P->beta;
     const double a = S->a_half, w = S->ad;
     const double ap1 = pow(a, P->p1), ap2 = pow(a, P->p2);
-    const double Sg = (t[0] + t[1]) / (dx * dx * N3);
+    const double Sg = P->gw * (t[0] + t[1]) / (dx * dx * N3);
     const double SV = (c1 * ap1 * t[2] / (double)beta + 0.5 * G * ap2 * t[3]) / N3;
     const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
     const double c = (-s - 2.0) * dt / (4.0 * a);
@@ -278,7 +257,7 @@ __device__ void aupdate_block(const double *part, int nblk, const DevParams *__r
     for (int j = 0; j < kMaxBeta; ++j) h[j] = 0.0;
     for (int j = 1; j <= beta - 1; ++j)
         h[j - 1] = dt * c1 * ap1 * binom_d(beta - 1, j) * ipow_d(g1, beta - 1 - j);
-    const double Cl = dt * alpha / (dx * dx), Cf = dt * bc, C2 = dt * G * ap2;
+    const double Cl = dt * alpha * P->gw / (dx * dx), Cf = dt * bc, C2 = dt * G * ap2;
     Coef<double> &cd = C->d;
     Coef<float> &cf = C->f;
     cd.Cl = Cl; cd.Cf = Cf; cd.dt = dt; cd.C2 = C2; cd.g1 = g1; cd.g2 = g2;
@@ -319,16 +298,15 @@ __global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *
 // ---------------------------------------------------------------- energies
 
 // Per-block sums at the synchronised time (FP64 per site):
-//  0,1: sum (v_i - r (a'/a) f_i)^2   2,3: sum |d+ f_i|^2 (raw)
+//  0,1: sum (v_i - r (a'/a) f_i)^2   2,3: raw gradient sums of f_i
 //  4: sum f1^beta   5: sum f1^2 f2^2
-template <typename T>
+template <typename T, int ST>
 __global__ void __launch_bounds__(256) k_energy_part(const T *__restrict__ d1, const T *__restrict__ d2,
                                                      const T *__restrict__ e1, const T *__restrict__ e2,
                                                      int N, const DevParams *__restrict__ P,
                                                      const DevScalars *__restrict__ S, double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N;
     const double h = 0.5 * P->dt, r = P->r;
     const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
     const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
@@ -339,12 +317,16 @@ __global__ void __launch_bounds__(256) k_energy_part(const T *__restrict__ d1, c
     for (int i = 0; i < kNEn; ++i) acc[i] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int x, y, z;
-        site_xyz(i, N, x, y, z);
-        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
-        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
-        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const Wrap w(i, N);
         // synchronised deviations d(k) = d(k+1/2) - dt/2 e(k)
+        auto sy1 = [&](int dx, int dy, int dz) {
+            const int64_t j = w(dx, dy, dz);
+            return (double)d1[j] - h * (double)e1[j];
+        };
+        auto sy2 = [&](int dx, int dy, int dz) {
+            const int64_t j = w(dx, dy, dz);
+            return (double)d2[j] - h * (double)e2[j];
+        };
         const double s1 = (double)d1[i] - h * (double)e1[i];
         const double s2 = (double)d2[i] - h * (double)e2[i];
         const double x1 = gs1 + s1, x2 = gs2 + s2;
@@ -352,14 +334,8 @@ __global__ void __launch_bounds__(256) k_energy_part(const T *__restrict__ d1, c
         const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
         acc[0] += q1 * q1;
         acc[1] += q2 * q2;
-        double t0 = ((double)d1[ix] - h * (double)e1[ix]) - s1;
-        double t1 = ((double)d1[iy] - h * (double)e1[iy]) - s1;
-        double t2 = ((double)d1[iz] - h * (double)e1[iz]) - s1;
-        acc[2] += t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = ((double)d2[ix] - h * (double)e2[ix]) - s2;
-        t1 = ((double)d2[iy] - h * (double)e2[iy]) - s2;
-        t2 = ((double)d2[iz] - h * (double)e2[iz]) - s2;
-        acc[3] += t0 * t0 + t1 * t1 + t2 * t2;
+        acc[2] += grad_raw<ST>(sy1, s1);
+        acc[3] += grad_raw<ST>(sy2, s2);
         acc[4] += ipow_d(x1, beta);
         acc[5] += x1 * x1 * x2 * x2;
     }
@@ -378,7 +354,7 @@ __global__ void __launch_bounds__(kStage2Threads) k_energy_final(const double *p
     const double N3 = P->N3, h = 0.5 * P->dt, s = P->s, r = P->r;
     const double ak = S->a_half - h * S->ad, ad = S->ad;
     const double K1 = 0.5 * t[0] / N3, K2 = 0.5 * t[1] / N3;
-    const double gf = 0.5 * pow(ak, -2.0 * s - 2.0) / (P->dx * P->dx * N3);
+    const double gf = 0.5 * pow(ak, -2.0 * s - 2.0) * P->gw / (P->dx * P->dx * N3);
     const double G1 = gf * t[2], G2 = gf * t[3];
     const double Pv = (P->c1 * pow(ak, P->p1) * t[4] / (double)P->beta + 0.5 * P->G * pow(ak, P->p2) * t[5]) / N3;
     const double rho = K1 + K2 + G1 + G2 + Pv;
@@ -395,9 +371,10 @@ __global__ void __launch_bounds__(kStage2Threads) k_energy_final(const double *p
 
 // Energy density and pressure per site at the synchronised time (eq. rho-pres
 // in program units): rho = sum_i K_i + G_i + V_pr, p = sum_i K_i - G_i/3 - V_pr,
-// K_i = (v_i - r (a'/a) f_i)^2/2, G_i = a^(-2s-2) |grad+ f_i|^2/2.  FP64 per
-// site; rho, p may be NULL.  Partials: sum rho, sum p.
-template <typename T, typename To>
+// K_i = (v_i - r (a'/a) f_i)^2/2, G_i = a^(-2s-2) grad2(f_i)/2 with grad2 the
+// gradient energy density of the stencil (forward differences |d+ f|^2 for 7
+// points).  FP64 per site; rho, p may be NULL.  Partials: sum rho, sum p.
+template <typename T, typename To, int ST>
 __global__ void __launch_bounds__(256) k_rho_p(const T *__restrict__ d1, const T *__restrict__ d2,
                                                const T *__restrict__ e1, const T *__restrict__ e2,
                                                int N, const DevParams *__restrict__ P,
@@ -405,35 +382,32 @@ __global__ void __launch_bounds__(256) k_rho_p(const T *__restrict__ d1, const T
                                                double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
-    const int64_t NN = (int64_t)N * N;
     const double h = 0.5 * P->dt, r = P->r, s = P->s;
     const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
     const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
     const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
-    const double gfac = 0.5 * pow(ak, -2.0 * s - 2.0) / (P->dx * P->dx);
+    const double gfac = 0.5 * pow(ak, -2.0 * s - 2.0) * P->gw / (P->dx * P->dx);
     const double cv1 = P->c1 * pow(ak, P->p1) / (double)P->beta, cv2 = 0.5 * P->G * pow(ak, P->p2);
     const int beta = P->beta;
     double acc[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int x, y, z;
-        site_xyz(i, N, x, y, z);
-        const int64_t ix = i + ((x + 1 == N) ? 1 - N : 1);
-        const int64_t iy = i + ((y + 1 == N) ? (1 - N) * (int64_t)N : (int64_t)N);
-        const int64_t iz = i + ((z + 1 == N) ? (1 - N) * NN : NN);
+        const Wrap w(i, N);
+        auto sy1 = [&](int dx, int dy, int dz) {
+            const int64_t j = w(dx, dy, dz);
+            return (double)d1[j] - h * (double)e1[j];
+        };
+        auto sy2 = [&](int dx, int dy, int dz) {
+            const int64_t j = w(dx, dy, dz);
+            return (double)d2[j] - h * (double)e2[j];
+        };
         const double s1 = (double)d1[i] - h * (double)e1[i];
         const double s2 = (double)d2[i] - h * (double)e2[i];
         const double x1 = gs1 + s1, x2 = gs2 + s2;
         const double q1 = (vb1 + (double)e1[i]) - r * hub * x1;
         const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
-        double t0 = ((double)d1[ix] - h * (double)e1[ix]) - s1;
-        double t1 = ((double)d1[iy] - h * (double)e1[iy]) - s1;
-        double t2 = ((double)d1[iz] - h * (double)e1[iz]) - s1;
-        double g = t0 * t0 + t1 * t1 + t2 * t2;
-        t0 = ((double)d2[ix] - h * (double)e2[ix]) - s2;
-        t1 = ((double)d2[iy] - h * (double)e2[iy]) - s2;
-        t2 = ((double)d2[iz] - h * (double)e2[iz]) - s2;
-        g += t0 * t0 + t1 * t1 + t2 * t2;
+        double g = grad_raw<ST>(sy1, s1);
+        g += grad_raw<ST>(sy2, s2);
         const double K = 0.5 * (q1 * q1 + q2 * q2), Gs = gfac * g;
         const double V = cv1 * ipow_d(x1, beta) + cv2 * x1 * x1 * x2 * x2;
         const double rr = K + Gs + V, pp = K - Gs / 3.0 - V;
@@ -528,15 +502,24 @@ void launch_fill_synthetic(int dtype, void *const s4[4], int N, DevScalars *S, h
 }
 
 
-void launch_input_moments(int in_dtype, const void *f1, const void *f2, const void *v1,
+template <typename Tin, int ST>
+static void input_moments_t(const void *f1, const void *f2, const void *v1, const void *v2, int N,
+                            int beta, double *part, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_input_moments<Tin, ST>), dim3(nblk), dim3(256), 0, st, (const Tin *)f1,
+                       (const Tin *)f2, (const Tin *)v1, (const Tin *)v2, N, beta, part);
+}
+
+void launch_input_moments(int stencil, int in_dtype, const void *f1, const void *f2, const void *v1,
                           const void *v2, int N, int beta, double *part, int nblk, hipStream_t st)
 {
-    if (in_dtype == 0)
-        hipLaunchKernelGGL(k_input_moments<float>, dim3(nblk), dim3(256), 0, st, (const float *)f1,
-                           (const float *)f2, (const float *)v1, (const float *)v2, N, beta, part);
-    else
-        hipLaunchKernelGGL(k_input_moments<double>, dim3(nblk), dim3(256), 0, st, (const double *)f1,
-                           (const double *)f2, (const double *)v1, (const double *)v2, N, beta, part);
+    if (stencil == 27) {
+        if (in_dtype == 0) input_moments_t<float, 27>(f1, f2, v1, v2, N, beta, part, nblk, st);
+        else input_moments_t<double, 27>(f1, f2, v1, v2, N, beta, part, nblk, st);
+    } else {
+        if (in_dtype == 0) input_moments_t<float, 7>(f1, f2, v1, v2, N, beta, part, nblk, st);
+        else input_moments_t<double, 7>(f1, f2, v1, v2, N, beta, part, nblk, st);
+    }
 }
 
 void launch_init_scalars(const double *part, int nblk, const DevParams *P, DevScalars *S,
@@ -567,15 +550,24 @@ void launch_init_fields(int dtype, int in_dtype, const void *f1, const void *f2,
     else init_fields_t<double, double>(f1, f2, v1, v2, d1, d2, e1, e2, N, P, S, st);
 }
 
-void launch_reduce(int dtype, const void *d1, const void *d2, int N, const double *bg_f, int beta,
-                   double *part, int nblk, hipStream_t st)
+template <typename T, int ST>
+static void reduce_t(const void *d1, const void *d2, int N, const double *bg_f, int beta, double *part,
+                     int nblk, hipStream_t st)
 {
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_reduce<float>, dim3(nblk), dim3(256), 0, st, (const float *)d1,
-                           (const float *)d2, N, bg_f, beta, part);
-    else
-        hipLaunchKernelGGL(k_reduce<double>, dim3(nblk), dim3(256), 0, st, (const double *)d1,
-                           (const double *)d2, N, bg_f, beta, part);
+    hipLaunchKernelGGL((k_reduce<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)d1, (const T *)d2, N,
+                       bg_f, beta, part);
+}
+
+void launch_reduce(int stencil, int dtype, const void *d1, const void *d2, int N, const double *bg_f,
+                   int beta, double *part, int nblk, hipStream_t st)
+{
+    if (stencil == 27) {
+        if (dtype == 0) reduce_t<float, 27>(d1, d2, N, bg_f, beta, part, nblk, st);
+        else reduce_t<double, 27>(d1, d2, N, bg_f, beta, part, nblk, st);
+    } else {
+        if (dtype == 0) reduce_t<float, 7>(d1, d2, N, bg_f, beta, part, nblk, st);
+        else reduce_t<double, 7>(d1, d2, N, bg_f, beta, part, nblk, st);
+    }
 }
 
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S, CoefPair *C,
@@ -589,15 +581,24 @@ void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st)
     hipLaunchKernelGGL(k_aupdate_ens, dim3(R), dim3(kStage2Threads), 0, st, tab);
 }
 
-void launch_energy(int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
-                   double *part, int nblk, double *out_dev, hipStream_t st)
+template <typename T, int ST>
+static void energy_t(const void *const s4[4], int N, const DevParams *P, const DevScalars *S, double *part,
+                     int nblk, hipStream_t st)
 {
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_energy_part<float>, dim3(nblk), dim3(256), 0, st, (const float *)s4[0],
-                           (const float *)s4[1], (const float *)s4[2], (const float *)s4[3], N, P, S, part);
-    else
-        hipLaunchKernelGGL(k_energy_part<double>, dim3(nblk), dim3(256), 0, st, (const double *)s4[0],
-                           (const double *)s4[1], (const double *)s4[2], (const double *)s4[3], N, P, S, part);
+    hipLaunchKernelGGL((k_energy_part<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0],
+                       (const T *)s4[1], (const T *)s4[2], (const T *)s4[3], N, P, S, part);
+}
+
+void launch_energy(int stencil, int dtype, const void *const s4[4], int N, const DevParams *P,
+                   const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st)
+{
+    if (stencil == 27) {
+        if (dtype == 0) energy_t<float, 27>(s4, N, P, S, part, nblk, st);
+        else energy_t<double, 27>(s4, N, P, S, part, nblk, st);
+    } else {
+        if (dtype == 0) energy_t<float, 7>(s4, N, P, S, part, nblk, st);
+        else energy_t<double, 7>(s4, N, P, S, part, nblk, st);
+    }
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, out_dev);
 }
 
@@ -620,22 +621,31 @@ void launch_get_fields(int dtype, int out_dtype, const void *const s4[4], void *
     else get_fields_t<double, double>(s4, out, N, P, S, synchronized, st);
 }
 
-template <typename T, typename To>
+template <typename T, typename To, int ST>
 static void rho_p_t(const void *const s4[4], void *rho, void *pr, int N, const DevParams *P,
                     const DevScalars *S, double *part, int nblk, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_rho_p<T, To>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0], (const T *)s4[1],
-                       (const T *)s4[2], (const T *)s4[3], N, P, S, (To *)rho, (To *)pr, part);
+    hipLaunchKernelGGL((k_rho_p<T, To, ST>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0],
+                       (const T *)s4[1], (const T *)s4[2], (const T *)s4[3], N, P, S, (To *)rho, (To *)pr,
+                       part);
 }
 
-void launch_rho_p(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+template <int ST>
+static void rho_p_s(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+                    const DevParams *P, const DevScalars *S, double *part, int nblk, hipStream_t st)
+{
+    if (dtype == 0 && out_dtype == 0) rho_p_t<float, float, ST>(s4, rho, pr, N, P, S, part, nblk, st);
+    else if (dtype == 0) rho_p_t<float, double, ST>(s4, rho, pr, N, P, S, part, nblk, st);
+    else if (out_dtype == 0) rho_p_t<double, float, ST>(s4, rho, pr, N, P, S, part, nblk, st);
+    else rho_p_t<double, double, ST>(s4, rho, pr, N, P, S, part, nblk, st);
+}
+
+void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
                   const DevParams *P, const DevScalars *S, double *part, int nblk, double *out_dev,
                   hipStream_t st)
 {
-    if (dtype == 0 && out_dtype == 0) rho_p_t<float, float>(s4, rho, pr, N, P, S, part, nblk, st);
-    else if (dtype == 0) rho_p_t<float, double>(s4, rho, pr, N, P, S, part, nblk, st);
-    else if (out_dtype == 0) rho_p_t<double, float>(s4, rho, pr, N, P, S, part, nblk, st);
-    else rho_p_t<double, double>(s4, rho, pr, N, P, S, part, nblk, st);
+    if (stencil == 27) rho_p_s<27>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
+    else rho_p_s<7>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
     hipLaunchKernelGGL(k_rho_p_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, out_dev);
 }
 

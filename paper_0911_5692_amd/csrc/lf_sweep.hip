@@ -33,63 +33,18 @@
 //
 // k_sweep_plain — one thread per site, neighbours straight from global
 //   memory, followed by the separate reduction k_reduce.  Kept as the simple
-//   reference variant (tile_y = 1).
-#include "lf_internal.h"
+//   reference variant (tile_y = 1); it also implements the 27-point stencil
+//   (ST = 27, the paper's own Laplacian, Sec. II.C).
+//
+// The LDS z-march of the 27-point stencil is k_sweep_lds27 (lf_sweep27.hip);
+// the launchers here dispatch to it.
+#include "lf_sweep_common.h"
 
 namespace lf {
 
-template <typename T>
-__device__ inline const Coef<T> &coef_of(const CoefPair *C);
-template <>
-__device__ inline const Coef<float> &coef_of<float>(const CoefPair *C) { return C->f; }
-template <>
-__device__ inline const Coef<double> &coef_of<double>(const CoefPair *C) { return C->d; }
-
-// Uniform per-step coefficients, read once per block (scalar loads).
-template <typename T, int NH>
-struct Coefs {
-    T Cl, Cf, dt, C2, g1, g2, two_g1, two_g2, g1sq;
-    T h[NH];
-    __device__ inline void load(const Coef<T> &c)
-    {
-        Cl = c.Cl; Cf = c.Cf; dt = c.dt; C2 = c.C2; g1 = c.g1; g2 = c.g2;
-        two_g1 = c.two_g1; two_g2 = c.two_g2; g1sq = c.g1sq;
-#pragma unroll
-        for (int j = 0; j < NH; ++j) h[j] = c.h[j];
-    }
-    // Velocity increments of both fields at one site from the raw 6-neighbour
-    // sums (s6a, s6b, already minus 6 d) and the deviations a = d1, b = d2.
-    __device__ inline void force(T a, T b, T s6a, T s6b, T &inc_a, T &inc_b) const
-    {
-        T hor = h[NH - 1];
-#pragma unroll
-        for (int j = NH - 2; j >= 0; --j) hor = hor * a + h[j];
-        const T t2 = g2 + b;
-        const T dv1 = hor * a + C2 * (a * t2 * t2 + g1 * b * (two_g2 + b));
-        const T dv2 = C2 * (a * (two_g1 + a) * t2 + g1sq * b);
-        inc_a = (Cl * s6a + Cf * a) - dv1;
-        inc_b = (Cl * s6b + Cf * b) - dv2;
-    }
-};
-
-template <typename T>
-__device__ inline T six_sum(T xm, T xp, T ym, T yp, T zm, T zp, T c)
-{
-    return (((xm + xp) + (ym + yp)) + (zm + zp)) - T(6) * c;
-}
-
-template <int NH>
-__device__ inline double potential_pow(double x)
-{
-    double r = x;
-#pragma unroll
-    for (int j = 0; j < NH; ++j) r *= x;  // x^(NH+1) = x^beta
-    return r;
-}
-
 // ------------------------------------------------------------ plain variant
 
-template <typename T, int NH>
+template <typename T, int NH, int ST>
 __global__ void __launch_bounds__(256) k_sweep_plain(const T *__restrict__ d1, const T *__restrict__ d2,
                                                      const T *__restrict__ e1, const T *__restrict__ e2,
                                                      T *__restrict__ d1n, T *__restrict__ d2n,
@@ -111,8 +66,20 @@ __global__ void __launch_bounds__(256) k_sweep_plain(const T *__restrict__ d1, c
     const int64_t zm = (z == 0) ? i + (int64_t)(N - 1) * NN : i - NN;
     const int64_t zp = (z == N - 1) ? i - (int64_t)(N - 1) * NN : i + NN;
     const T a = d1[i], b = d2[i];
-    const T la = six_sum(d1[xm], d1[xp], d1[ym], d1[yp], d1[zm], d1[zp], a);
-    const T lb = six_sum(d2[xm], d2[xp], d2[ym], d2[yp], d2[zm], d2[zp], b);
+    T la, lb;
+    if constexpr (ST == 7) {
+        la = six_sum(d1[xm], d1[xp], d1[ym], d1[yp], d1[zm], d1[zp], a);
+        lb = six_sum(d2[xm], d2[xp], d2[ym], d2[yp], d2[zm], d2[zp], b);
+    } else {
+        auto idx = [&](int dx, int dy, int dz) {
+            const int64_t ox = dx < 0 ? xm - i : (dx > 0 ? xp - i : 0);
+            const int64_t oy = dy < 0 ? ym - i : (dy > 0 ? yp - i : 0);
+            const int64_t oz = dz < 0 ? zm - i : (dz > 0 ? zp - i : 0);
+            return i + ox + oy + oz;
+        };
+        la = lap_raw<27, T>([&](int dx, int dy, int dz) { return d1[idx(dx, dy, dz)]; }, a);
+        lb = lap_raw<27, T>([&](int dx, int dy, int dz) { return d2[idx(dx, dy, dz)]; }, b);
+    }
     T ia, ib;
     c.force(a, b, la, lb, ia, ib);
     const T ea = e1[i] + ia, eb = e2[i] + ib;
@@ -123,16 +90,6 @@ __global__ void __launch_bounds__(256) k_sweep_plain(const T *__restrict__ d1, c
 }
 
 // ------------------------------------------------------------ LDS z-march
-
-// Hardware places block b on XCD (b mod 8).  Give each XCD a contiguous range
-// of logical tiles, so that tiles sharing halo rows run on the same L2.
-__device__ inline int xcd_remap(int b, int nb)
-{
-    constexpr int kXcd = 8;
-    const int q = nb / kXcd;
-    if (b >= q * kXcd) return b;
-    return (b % kXcd) * q + b / kXcd;
-}
 
 // One block's work: the tile x0.., y0.. of an N^3 lattice over planes
 // [z0, z1), writing its four partial sums to part_row[0..3].
@@ -443,34 +400,39 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_ens(
 
 // ------------------------------------------------------------ launchers
 
-template <typename T, int NH>
+template <typename T, int NH, int ST>
 static void sweep_plain_t(const void *const in[4], void *const out[4], int N, const CoefPair *C,
                           hipStream_t st)
 {
     dim3 grid((N + 63) / 64, (N + 3) / 4, N), block(64, 4);
-    hipLaunchKernelGGL((k_sweep_plain<T, NH>), grid, block, 0, st, (const T *)in[0], (const T *)in[1],
+    hipLaunchKernelGGL((k_sweep_plain<T, NH, ST>), grid, block, 0, st, (const T *)in[0], (const T *)in[1],
                        (const T *)in[2], (const T *)in[3], (T *)out[0], (T *)out[1], (T *)out[2],
                        (T *)out[3], N, C);
 }
 
-template <typename T>
+template <typename T, int ST>
 static void sweep_plain_b(int beta, const void *const in[4], void *const out[4], int N,
                           const CoefPair *C, hipStream_t st)
 {
     switch (beta) {
-    case 2: sweep_plain_t<T, 1>(in, out, N, C, st); break;
-    case 3: sweep_plain_t<T, 2>(in, out, N, C, st); break;
-    case 4: sweep_plain_t<T, 3>(in, out, N, C, st); break;
-    case 5: sweep_plain_t<T, 4>(in, out, N, C, st); break;
-    default: sweep_plain_t<T, 5>(in, out, N, C, st); break;
+    case 2: sweep_plain_t<T, 1, ST>(in, out, N, C, st); break;
+    case 3: sweep_plain_t<T, 2, ST>(in, out, N, C, st); break;
+    case 4: sweep_plain_t<T, 3, ST>(in, out, N, C, st); break;
+    case 5: sweep_plain_t<T, 4, ST>(in, out, N, C, st); break;
+    default: sweep_plain_t<T, 5, ST>(in, out, N, C, st); break;
     }
 }
 
-void launch_sweep_plain(int dtype, int beta, const void *const in[4], void *const out[4], int N,
-                        const CoefPair *C, hipStream_t st)
+void launch_sweep_plain(int stencil, int dtype, int beta, const void *const in[4], void *const out[4],
+                        int N, const CoefPair *C, hipStream_t st)
 {
-    if (dtype == 0) sweep_plain_b<float>(beta, in, out, N, C, st);
-    else sweep_plain_b<double>(beta, in, out, N, C, st);
+    if (stencil == 27) {
+        if (dtype == 0) sweep_plain_b<float, 27>(beta, in, out, N, C, st);
+        else sweep_plain_b<double, 27>(beta, in, out, N, C, st);
+    } else {
+        if (dtype == 0) sweep_plain_b<float, 7>(beta, in, out, N, C, st);
+        else sweep_plain_b<double, 7>(beta, in, out, N, C, st);
+    }
 }
 
 int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk)
@@ -544,8 +506,9 @@ static int occ_y(int tile_x, int tile_y, int beta)
     }
 }
 
-int sweep_lds_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta)
+int sweep_lds_blocks_per_cu(int stencil, int dtype, int tile_x, int tile_y, int beta)
 {
+    if (stencil == 27) return sweep_lds27_blocks_per_cu(dtype, tile_x, tile_y, beta);
     return dtype == 0 ? occ_y<float>(tile_x, tile_y, beta) : occ_y<double>(tile_x, tile_y, beta);
 }
 
@@ -585,18 +548,20 @@ static void sweep_ens_y(int tile_x, int tile_y, int beta, const EnsEntry *tab, c
     }
 }
 
-void launch_sweep_ens(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
+void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
                       const int4 *items, int nitems, int grid, int parity, hipStream_t st)
 {
-    if (dtype == 0) sweep_ens_y<float>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+    if (stencil == 27) launch_sweep_ens27(dtype, tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+    else if (dtype == 0) sweep_ens_y<float>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
     else sweep_ens_y<double>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
 }
 
-void launch_sweep_lds(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+void launch_sweep_lds(int stencil, int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
                       void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
                       hipStream_t st)
 {
-    if (dtype == 0) sweep_lds_y<float>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+    if (stencil == 27) launch_sweep_lds27(dtype, tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+    else if (dtype == 0) sweep_lds_y<float>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
     else sweep_lds_y<double>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
 }
 

@@ -1,0 +1,511 @@
+// Fused kick-drift sweep with the 27-point Laplacian (Sainio,
+// arXiv:0911.5692, Sec. II.C: second-order accurate, fourth-order isotropic;
+// weights (centre, face, edge, corner) = (-128, 14, 3, 1)/30), gfx950.
+//
+// Same per-site update as the 7-point sweep (lf_sweep.hip), with the raw
+// stencil sum in place of S6.  The 3x3x3 neighbourhood is never held in LDS
+// at once: for every plane p and site, two in-plane partial sums are formed
+// while p is staged,
+//   A(p) = 14 c + 3 S4 + S4d      (what p contributes to the planes p-1, p+1)
+//   B(p) = -128 c + 14 S4 + 3 S4d (what p contributes to itself)
+// with c the site, S4 its 4 in-plane face neighbours and S4d its 4 in-plane
+// diagonal neighbours, so that raw Lap(z) = B(z) + A(z-1) + A(z+1).  A block
+// keeps A(z-1), A(z), B(z) per site in registers; one staged plane (z+1) per
+// iteration completes the Laplacian of plane z.
+//
+// Reductions for the next a'': the gradient energy of the 27-point stencil is
+// its Dirichlet form, a sum over lattice bonds of w_b (f(p) - f(q))^2.  Each
+// bond is counted by exactly one (tile, plane):
+//   * a bond between two z-planes is counted at the upper plane;
+//   * a bond whose xy-projection crosses a tile border is counted by the tile
+//     whose "lower ring" (row y0-1 from x0-1 to x0+TX, column x0-1 from y0 to
+//     y0+TY-1) holds the other end; among the 8 xy-neighbour relations of two
+//     tiles exactly one of them has that property.
+// So a block needs the new values on its interior and its lower ring for the
+// planes z and z-1: the ring values are computed redundantly (never stored),
+// as is the plane z0-1 below the chunk, and the bonds counted are
+//   interior(z) - {interior, ring}(z) through the 4 in-plane offsets
+//     (-1,0), (0,-1), (-1,-1), (+1,-1);
+//   interior(z) - {interior, ring}(z-1) through the 9 offsets below;
+//   ring(z) - interior(z-1), and the ring column's in-plane (+1,-1) bond
+//   into the interior.
+// Per site the squared differences are summed by bond type in the working
+// precision and the weighted site sum 14 F + 3 E + C is accumulated in FP64.
+//
+// LDS per block (FP32, 128 x 8 tile): two staged planes of (TX+4)(TY+3) and
+// three new-value planes of (TX+2)(TY+1), both fields: 51 KB, 3 blocks/CU.
+#include "lf_sweep_common.h"
+
+#include <type_traits>
+
+namespace lf {
+
+namespace {
+
+// One block's work: tile (x0, y0) of an N^3 lattice over planes [z0, z1),
+// writing its four partial sums to part_row[0..3].
+template <typename T, int NH, int TX, int TY>
+__device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *__restrict__ d2,
+                                             const T *__restrict__ e1, const T *__restrict__ e2,
+                                             T *__restrict__ d1n, T *__restrict__ d2n,
+                                             T *__restrict__ e1n, T *__restrict__ e2n, const int N,
+                                             const int x0, const int y0, const int z0, const int z1,
+                                             const CoefPair *__restrict__ C, double *__restrict__ part_row)
+{
+    constexpr int RPR = 256 / TX;                // rows per round of 256 threads
+    constexpr int KI = TY / RPR;                 // interior sites per thread per plane
+    constexpr int LW = TX + 4, LH = TY + 3;      // staged plane: x0-2 .. x0+TX+1, y0-2 .. y0+TY
+    constexpr int NW = TX + 2, NHT = TY + 1;     // new values: x0-1 .. x0+TX, y0-1 .. y0+TY-1
+    constexpr int NRING = TX + 2 + TY;           // row y0-1 (x0-1 .. x0+TX), column x0-1 (y0 ..)
+    constexpr int NHALO = 2 * (TX + 4) + 3 * TY + 2;
+    static_assert(256 % TX == 0 && TY % RPR == 0 && NRING <= 256 && NHALO <= 512, "tile shape");
+    // staged planes: plane z+1 is read from sd[cur] while z+2 is written to
+    // sd[cur ^ 1]; new values: three planes in rotation (z, z-1 read after
+    // the barrier while the next iteration writes the third)
+    __shared__ T sd[2][2][LH * LW];
+    __shared__ T sn[3][2][NHT * NW];
+
+    Coefs<T, NH> c;
+    c.load(coef_of<T>(C));
+    const double g1n = C->g1n, g2n = C->g2n;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t NN = (int64_t)N * N;
+    auto wrapc = [N](int v) { return ((v % N) + N) % N; };
+    const int wv = min(TX, N - x0), hv = min(TY, N - y0);  // valid interior extent
+
+    // interior sites (x0 + t % TX, y0 + t / TX + RPR k)
+    int goff[KI], lsd[KI], lsn[KI];
+    bool act[KI], okx[KI], oky[KI], ok4[KI];
+    const int cx = t % TX, cy = t / TX;
+    const int xi = x0 + cx;
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+        const int yl = cy + RPR * k;
+        const int y = y0 + yl;
+        act[k] = (xi < N) && (y < N);
+        goff[k] = (y % N) * N + (xi % N);  // in-bounds even when inactive
+        lsd[k] = (yl + 2) * LW + cx + 2;
+        lsn[k] = (yl + 1) * NW + cx + 1;
+        okx[k] = cx + 1 < wv;              // (cx+1, yl) is interior
+        oky[k] = yl + 1 < hv;              // (cx, yl+1) is interior
+        ok4[k] = (yl == 0) || okx[k];      // (cx+1, yl-1) is interior or ring
+    }
+    // ring site of this thread (t < NRING): new value only, never stored
+    const bool hasr = t < NRING;
+    const bool rrow = t < TX + 2;
+    const int rlx = rrow ? t - 1 : -1, rly = rrow ? -1 : t - (TX + 2);
+    const int roff = hasr ? wrapc(y0 + rly) * N + wrapc(x0 + rlx) : 0;
+    const int rlsd = hasr ? (rly + 2) * LW + rlx + 2 : 0;
+    const int rlsn = hasr ? (rly + 1) * NW + rlx + 1 : 0;
+    // the ring's bonds into the interior: three to plane z-1 (index rq,
+    // validity rv; the middle one an edge, the outer two corners) and, for
+    // the ring column, one in-plane edge (rqi, rvi)
+    int rq[3], rqi = rlsn;
+    bool rv[3], rvi = false;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (rrow) {
+            const int x = rlx + j - 1;  // interior (x, 0)
+            rv[j] = hasr && x >= 0 && x < wv;
+            rq[j] = rv[j] ? NW + x + 1 : rlsn;
+        } else {
+            const int y = rly + j - 1;  // interior (0, y)
+            rv[j] = hasr && rly < hv && y >= 0 && y < hv;
+            rq[j] = rv[j] ? (y + 1) * NW + 1 : rlsn;
+        }
+    }
+    if (hasr && !rrow && rly >= 1 && rly < hv) {
+        rvi = true;
+        rqi = rly * NW + 1;  // interior (0, rly - 1)
+    }
+    // halo cells of this thread (t and t + 256 below NHALO): staged-plane
+    // border that no computed site covers
+    bool hash[2];
+    int hoff[2], hlsd[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int hc = t + 256 * m;
+        hash[m] = hc < NHALO;
+        int hlx, hly;  // local coordinates
+        if (hc < TX + 4) { hlx = hc - 2; hly = -2; }
+        else if (hc < 2 * (TX + 4)) { hlx = hc - (TX + 4) - 2; hly = TY; }
+        else if (hc < 2 * (TX + 4) + TY + 1) { hlx = -2; hly = hc - 2 * (TX + 4) - 1; }
+        else if (hc < 2 * (TX + 4) + 2 * (TY + 1)) { hlx = TX + 1; hly = hc - 2 * (TX + 4) - (TY + 1) - 1; }
+        else { hlx = TX; hly = hc - 2 * (TX + 4) - 2 * (TY + 1); }
+        if (!hash[m]) { hlx = 0; hly = 0; }
+        hoff[m] = wrapc(y0 + hly) * N + wrapc(x0 + hlx);
+        hlsd[m] = (hly + 2) * LW + hlx + 2;
+    }
+    // plane base pointers: z stays within [z0 - 3, z1 + 2], one wrap suffices
+    auto plane = [&](const T *p, int z) {
+        const int zw = z < 0 ? z + N : (z >= N ? z - N : z);
+        return p + (int64_t)zw * NN;
+    };
+
+    // Registers per site and field: d(z) qc, d(z+1) qp, d(z+2) nd (staged this
+    // iteration), e(z) ev, partial sums A(z-1) am, A(z) ac, B(z) bc; loads in
+    // flight for the next iteration: d(z+3) ld, e(z+1) le, halo(z+3) lh.
+    T qc1[KI], qp1[KI], nd1[KI], ld1[KI], ev1[KI], le1[KI], am1[KI], ac1[KI], bc1[KI];
+    T qc2[KI], qp2[KI], nd2[KI], ld2[KI], ev2[KI], le2[KI], am2[KI], ac2[KI], bc2[KI];
+    T rqc1 = 0, rqp1 = 0, rnd1 = 0, rld1 = 0, rev1 = 0, rle1 = 0, ram1 = 0, rac1 = 0, rbc1 = 0;
+    T rqc2 = 0, rqp2 = 0, rnd2 = 0, rld2 = 0, rev2 = 0, rle2 = 0, ram2 = 0, rac2 = 0, rbc2 = 0;
+    T hv1[2] = {0, 0}, hv2[2] = {0, 0}, lh1[2] = {0, 0}, lh2[2] = {0, 0};
+
+    const int zs = z0 - 3;  // first iteration: plane z0-2 staged
+    {
+        const T *a1 = plane(d1, z0 - 2), *a2 = plane(d2, z0 - 2);
+        const T *b1 = plane(d1, z0 - 1), *b2 = plane(d2, z0 - 1);
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            qp1[k] = a1[goff[k]]; qp2[k] = a2[goff[k]];
+            nd1[k] = b1[goff[k]]; nd2[k] = b2[goff[k]];
+            qc1[k] = 0; qc2[k] = 0; ev1[k] = 0; ev2[k] = 0;
+            am1[k] = 0; am2[k] = 0; ac1[k] = 0; ac2[k] = 0; bc1[k] = 0; bc2[k] = 0;
+            sd[0][0][lsd[k]] = qp1[k];
+            sd[0][1][lsd[k]] = qp2[k];
+        }
+        if (hasr) {
+            rqp1 = a1[roff]; rqp2 = a2[roff];
+            rnd1 = b1[roff]; rnd2 = b2[roff];
+            sd[0][0][rlsd] = rqp1;
+            sd[0][1][rlsd] = rqp2;
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            if (hash[m]) {
+                sd[0][0][hlsd[m]] = a1[hoff[m]];
+                sd[0][1][hlsd[m]] = a2[hoff[m]];
+                hv1[m] = b1[hoff[m]];
+                hv2[m] = b2[hoff[m]];
+            }
+        __syncthreads();
+    }
+
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int cur = 0;
+    int nb_cur = 0, nb_prev = 2;  // new-value planes of z and z-1
+    for (int z = zs; z < z1; ++z) {
+        // loads for the next iteration: d(z+3), halo(z+3), e(z+1)
+        {
+            const int pz = z + 3;
+            const bool need_d = pz <= z1, need_e = (z + 1 >= z0 - 1) && (z + 1 <= z1 - 1);
+            const T *a1 = plane(d1, pz), *a2 = plane(d2, pz);
+            const T *b1 = plane(e1, z + 1), *b2 = plane(e2, z + 1);
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                ld1[k] = need_d ? a1[goff[k]] : T(0);
+                ld2[k] = need_d ? a2[goff[k]] : T(0);
+                le1[k] = need_e ? b1[goff[k]] : T(0);
+                le2[k] = need_e ? b2[goff[k]] : T(0);
+            }
+            rld1 = (hasr && need_d) ? a1[roff] : T(0);
+            rld2 = (hasr && need_d) ? a2[roff] : T(0);
+            rle1 = (hasr && need_e) ? b1[roff] : T(0);
+            rle2 = (hasr && need_e) ? b2[roff] : T(0);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                lh1[m] = (hash[m] && need_d) ? a1[hoff[m]] : T(0);
+                lh2[m] = (hash[m] && need_d) ? a2[hoff[m]] : T(0);
+            }
+        }
+
+        const bool upd = z >= z0 - 1;  // plane z is updated (z0-1: ring only for the reductions)
+        const bool live = z >= z0;     // plane z is stored and reduced
+        const T *s0 = sd[cur][0], *s1 = sd[cur][1];
+        T *n0 = sn[nb_cur][0], *n1 = sn[nb_cur][1];
+        T an1[KI], an2[KI], bn1[KI], bn2[KI], na1[KI], na2[KI];
+        // partial sums of the staged plane z+1, and the update of plane z
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int l = lsd[k];
+            const T f1 = (s0[l - 1] + s0[l + 1]) + (s0[l - LW] + s0[l + LW]);
+            const T g1 = (s0[l - LW - 1] + s0[l - LW + 1]) + (s0[l + LW - 1] + s0[l + LW + 1]);
+            const T f2 = (s1[l - 1] + s1[l + 1]) + (s1[l - LW] + s1[l + LW]);
+            const T g2 = (s1[l - LW - 1] + s1[l - LW + 1]) + (s1[l + LW - 1] + s1[l + LW + 1]);
+            an1[k] = (T(14) * qp1[k] + T(3) * f1) + g1;
+            bn1[k] = (T(-128) * qp1[k] + T(14) * f1) + T(3) * g1;
+            an2[k] = (T(14) * qp2[k] + T(3) * f2) + g2;
+            bn2[k] = (T(-128) * qp2[k] + T(14) * f2) + T(3) * g2;
+            T ia, ib;
+            c.force(qc1[k], qc2[k], (bc1[k] + am1[k]) + an1[k], (bc2[k] + am2[k]) + an2[k], ia, ib);
+            const T ea = ev1[k] + ia, eb = ev2[k] + ib;
+            na1[k] = qc1[k] + c.dt * ea;
+            na2[k] = qc2[k] + c.dt * eb;
+            if (live && act[k]) {
+                T *o_e1 = const_cast<T *>(plane(e1n, z)), *o_e2 = const_cast<T *>(plane(e2n, z));
+                T *o_d1 = const_cast<T *>(plane(d1n, z)), *o_d2 = const_cast<T *>(plane(d2n, z));
+                // streamed once: non-temporal, so L2 keeps the halo rows instead
+                __builtin_nontemporal_store(ea, o_e1 + goff[k]);
+                __builtin_nontemporal_store(eb, o_e2 + goff[k]);
+                __builtin_nontemporal_store(na1[k], o_d1 + goff[k]);
+                __builtin_nontemporal_store(na2[k], o_d2 + goff[k]);
+            }
+            if (upd) {
+                n0[lsn[k]] = na1[k];
+                n1[lsn[k]] = na2[k];
+            }
+        }
+        T rna1 = 0, rna2 = 0, ran1 = 0, ran2 = 0, rbn1 = 0, rbn2 = 0;
+        if (hasr) {
+            const int l = rlsd;
+            const T f1 = (s0[l - 1] + s0[l + 1]) + (s0[l - LW] + s0[l + LW]);
+            const T g1 = (s0[l - LW - 1] + s0[l - LW + 1]) + (s0[l + LW - 1] + s0[l + LW + 1]);
+            const T f2 = (s1[l - 1] + s1[l + 1]) + (s1[l - LW] + s1[l + LW]);
+            const T g2 = (s1[l - LW - 1] + s1[l - LW + 1]) + (s1[l + LW - 1] + s1[l + LW + 1]);
+            ran1 = (T(14) * rqp1 + T(3) * f1) + g1;
+            rbn1 = (T(-128) * rqp1 + T(14) * f1) + T(3) * g1;
+            ran2 = (T(14) * rqp2 + T(3) * f2) + g2;
+            rbn2 = (T(-128) * rqp2 + T(14) * f2) + T(3) * g2;
+            T ia, ib;
+            c.force(rqc1, rqc2, (rbc1 + ram1) + ran1, (rbc2 + ram2) + ran2, ia, ib);
+            rna1 = rqc1 + c.dt * (rev1 + ia);
+            rna2 = rqc2 + c.dt * (rev2 + ib);
+            if (upd) {
+                n0[rlsn] = rna1;
+                n1[rlsn] = rna2;
+            }
+        }
+        // stage plane z+2 into the other buffer (loaded one iteration ago)
+        if (z + 2 <= z1) {
+            T *t0 = sd[cur ^ 1][0], *t1 = sd[cur ^ 1][1];
+#pragma unroll
+            for (int k = 0; k < KI; ++k) { t0[lsd[k]] = nd1[k]; t1[lsd[k]] = nd2[k]; }
+            if (hasr) { t0[rlsd] = rnd1; t1[rlsd] = rnd2; }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                if (hash[m]) { t0[hlsd[m]] = hv1[m]; t1[hlsd[m]] = hv2[m]; }
+        }
+        __syncthreads();
+
+        if (live) {
+            const T *p0 = sn[nb_cur][0], *p1 = sn[nb_cur][1];      // plane z
+            const T *m0 = sn[nb_prev][0], *m1 = sn[nb_prev][1];    // plane z-1
+            // bonds of interior site k; a bond to a position outside the
+            // interior and ring reads the site itself (index l) and adds 0
+            auto bonds = [&](const T *P, const T *M, const int l, const T v, const int k) {
+                auto sq = [&](T u) { const T d = v - u; return d * d; };
+                const bool oxy = okx[k] && oky[k];
+                const T F = (sq(P[l - 1]) + sq(P[l - NW])) + sq(M[l]);
+                T E = sq(P[l - NW - 1]) + (ok4[k] ? sq(P[ok4[k] ? l - NW + 1 : l]) : T(0));
+                E += sq(M[l - 1]) + sq(M[l - NW]);
+                E += okx[k] ? sq(M[okx[k] ? l + 1 : l]) : T(0);
+                E += oky[k] ? sq(M[oky[k] ? l + NW : l]) : T(0);
+                T Cn = sq(M[l - NW - 1]) + (ok4[k] ? sq(M[ok4[k] ? l - NW + 1 : l]) : T(0));
+                Cn += oky[k] ? sq(M[oky[k] ? l + NW - 1 : l]) : T(0);
+                Cn += oxy ? sq(M[oxy ? l + NW + 1 : l]) : T(0);
+                return (double)((T(14) * F + T(3) * E) + Cn);
+            };
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                if (!act[k]) continue;
+                const int l = lsn[k];
+                acc0 += bonds(p0, m0, l, na1[k], k);
+                acc1 += bonds(p1, m1, l, na2[k], k);
+                const double x1 = g1n + (double)na1[k], x2 = g2n + (double)na2[k];
+                acc2 += potential_pow<NH>(x1);
+                acc3 += x1 * x1 * x2 * x2;
+            }
+            if (hasr) {
+                auto rb = [&](const T *P, const T *M, const T v) {
+                    auto sq = [&](T u) { const T d = v - u; return d * d; };
+                    const T E = (rv[1] ? sq(M[rq[1]]) : T(0)) + (rvi ? sq(P[rqi]) : T(0));
+                    const T Cn = (rv[0] ? sq(M[rq[0]]) : T(0)) + (rv[2] ? sq(M[rq[2]]) : T(0));
+                    return (double)(T(3) * E + Cn);
+                };
+                acc0 += rb(p0, m0, rna1);
+                acc1 += rb(p1, m1, rna2);
+            }
+        }
+
+        // rotate the queues
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            am1[k] = ac1[k]; ac1[k] = an1[k]; bc1[k] = bn1[k];
+            am2[k] = ac2[k]; ac2[k] = an2[k]; bc2[k] = bn2[k];
+            qc1[k] = qp1[k]; qp1[k] = nd1[k]; nd1[k] = ld1[k];
+            qc2[k] = qp2[k]; qp2[k] = nd2[k]; nd2[k] = ld2[k];
+            ev1[k] = le1[k]; ev2[k] = le2[k];
+        }
+        ram1 = rac1; rac1 = ran1; rbc1 = rbn1;
+        ram2 = rac2; rac2 = ran2; rbc2 = rbn2;
+        rqc1 = rqp1; rqp1 = rnd1; rnd1 = rld1;
+        rqc2 = rqp2; rqp2 = rnd2; rnd2 = rld2;
+        rev1 = rle1; rev2 = rle2;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) { hv1[m] = lh1[m]; hv2[m] = lh2[m]; }
+        cur ^= 1;
+        nb_prev = nb_cur;
+        nb_cur = nb_cur == 2 ? 0 : nb_cur + 1;
+    }
+
+    // block partial sums, fixed order
+    double v[4] = {acc0, acc1, acc2, acc3};
+    __shared__ double red[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[i][w] = v[i];
+    }
+    __syncthreads();
+    if (t < 4) part_row[t] = ((red[t][0] + red[t][1]) + red[t][2]) + red[t][3];
+}
+
+}  // namespace
+
+// Waves per SIMD to compile for: as many blocks as the LDS of a CU (160 KB)
+// holds, each block one wave per SIMD, at most 3 in FP32 (168 VGPRs) and 2 in
+// FP64 (which needs more registers).
+template <typename T, int TX, int TY>
+constexpr int sweep27_waves()
+{
+    constexpr int lds = (int)sizeof(T) * (2 * 2 * (TY + 3) * (TX + 4) + 3 * 2 * (TY + 1) * (TX + 2));
+    constexpr int by_lds = 160 * 1024 / lds;
+    constexpr int by_regs = sizeof(T) == 4 ? 3 : 2;
+    return by_lds < by_regs ? (by_lds < 1 ? 1 : by_lds) : by_regs;
+}
+#define LF_SWEEP27_WAVES(T) (sweep27_waves<T, TX, TY>())
+
+template <typename T, int NH, int TX, int TY>
+__global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_lds27(
+    const T *__restrict__ d1, const T *__restrict__ d2, const T *__restrict__ e1, const T *__restrict__ e2,
+    T *__restrict__ d1n, T *__restrict__ d2n, T *__restrict__ e1n, T *__restrict__ e2n, const int N,
+    const int zchunk, const int ntx, const int nty, const CoefPair *__restrict__ C, double *__restrict__ part)
+{
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, b = tile / ntx;
+    const int ty = b % nty;
+    const int tz = b / nty;
+    const int z0 = tz * zchunk;
+    sweep_tile27<T, NH, TX, TY>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, tx * TX, ty * TY, z0,
+                                min(z0 + zchunk, N), C, part + (size_t)tile * kNPart);
+}
+
+template <typename T, int NH, int TX, int TY>
+__global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_ens27(
+    const EnsEntry *__restrict__ tab, const int4 *__restrict__ items, const int nitems, const int parity)
+{
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int4 it = items[i];  // x: realization, y: tile index within it, z: partial row
+        const EnsEntry &e = tab[it.x];
+        const int tx = it.y % e.ntx, r2 = it.y / e.ntx, ty = r2 % e.nty, tz = r2 / e.nty;
+        const int z0 = tz * e.zchunk;
+        const T *const *in = (const T *const *)e.buf[parity];
+        T *const *out = (T *const *)e.buf[parity ^ 1];
+        sweep_tile27<T, NH, TX, TY>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
+                                    tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
+                                    e.part + (size_t)it.z * kNPart);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+namespace {
+
+// Calls f.template operator()<NH>() for the beta of the model.
+template <typename F>
+void with_nh(int beta, F &&f)
+{
+    switch (beta) {
+    case 2: f(std::integral_constant<int, 1>{}); break;
+    case 3: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 3>{}); break;
+    case 5: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 5>{}); break;
+    }
+}
+
+// Calls f(TX, TY) as integral constants for the supported tiles
+// 64x4, 64x8, 64x16, 128x4, 128x8.
+template <typename F>
+void with_tile(int tile_x, int tile_y, F &&f)
+{
+    using std::integral_constant;
+    if (tile_x == 128) {
+        if (tile_y == 4) f(integral_constant<int, 128>{}, integral_constant<int, 4>{});
+        else f(integral_constant<int, 128>{}, integral_constant<int, 8>{});
+        return;
+    }
+    switch (tile_y) {
+    case 4: f(integral_constant<int, 64>{}, integral_constant<int, 4>{}); break;
+    case 8: f(integral_constant<int, 64>{}, integral_constant<int, 8>{}); break;
+    default: f(integral_constant<int, 64>{}, integral_constant<int, 16>{}); break;
+    }
+}
+
+template <typename T>
+void lds27_t(int tile_x, int tile_y, int beta, const void *const in[4], void *const out[4], int N,
+             int zchunk, const CoefPair *C, double *part, hipStream_t st)
+{
+    with_tile(tile_x, tile_y, [&](auto tx, auto ty) {
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        with_nh(beta, [&](auto nh) {
+            constexpr int NH = decltype(nh)::value;
+            const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY, nzc = (N + zchunk - 1) / zchunk;
+            hipLaunchKernelGGL((k_sweep_lds27<T, NH, TX, TY>), dim3(ntx * nty * nzc), dim3(256), 0, st,
+                               (const T *)in[0], (const T *)in[1], (const T *)in[2], (const T *)in[3],
+                               (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3], N, zchunk, ntx, nty, C,
+                               part);
+        });
+    });
+}
+
+template <typename T>
+void ens27_t(int tile_x, int tile_y, int beta, const EnsEntry *tab, const int4 *items, int nitems, int grid,
+             int parity, hipStream_t st)
+{
+    with_tile(tile_x, tile_y, [&](auto tx, auto ty) {
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        with_nh(beta, [&](auto nh) {
+            constexpr int NH = decltype(nh)::value;
+            hipLaunchKernelGGL((k_sweep_ens27<T, NH, TX, TY>), dim3(grid), dim3(256), 0, st, tab, items, nitems,
+                               parity);
+        });
+    });
+}
+
+template <typename T>
+int occ27_t(int tile_x, int tile_y, int beta)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    with_tile(tile_x, tile_y, [&](auto tx, auto ty) {
+        constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
+        with_nh(beta, [&](auto nh) {
+            constexpr int NH = decltype(nh)::value;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_lds27<T, NH, TX, TY>, 256, 0);
+        });
+    });
+    return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace
+
+void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+                        void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
+                        hipStream_t st)
+{
+    if (dtype == 0) lds27_t<float>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+    else lds27_t<double>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+}
+
+void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
+                        const int4 *items, int nitems, int grid, int parity, hipStream_t st)
+{
+    if (dtype == 0) ens27_t<float>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+    else ens27_t<double>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+}
+
+int sweep_lds27_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta)
+{
+    return dtype == 0 ? occ27_t<float>(tile_x, tile_y, beta) : occ27_t<double>(tile_x, tile_y, beta);
+}
+
+}  // namespace lf

@@ -33,12 +33,13 @@ DEFAULT_TUNE_CACHE = os.environ.get(
 
 def autotune(N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float, s: float,
              kappa2: float, dtype: torch.dtype = torch.float32, device="cuda",
-             cache_path: str | None = DEFAULT_TUNE_CACHE) -> dict:
-    """Fastest sweep launch shape for this lattice size, dtype and beta on the
-    current device (liblf's lf_autotune; cached per architecture in a JSONL
-    file).  Returns dict(tile_x, tile_y, zchunk, ms) (ms = -1 on a cache hit)."""
+             cache_path: str | None = DEFAULT_TUNE_CACHE, stencil: int = 7) -> dict:
+    """Fastest sweep launch shape for this lattice size, dtype, beta and
+    stencil on the current device (liblf's lf_autotune; cached per
+    architecture in a JSONL file).  Returns dict(tile_x, tile_y, zchunk, ms)
+    (ms = -1 on a cache hit)."""
     p = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1), float(G), float(r),
-               float(s), float(kappa2), 0, 0, 0, 0)
+               float(s), float(kappa2), 0, 0, 0, int(stencil))
     size = ctypes.c_size_t()
     check(lib().lf_autotune_workspace_bytes(ctypes.byref(p), ctypes.byref(size)))
     ws = torch.empty(size.value, dtype=torch.uint8, device=device)
@@ -60,20 +61,21 @@ class Lattice:
     Parameters are program units: box side L, time step dt, potential
     V_pr = c1 a^p1 f1^beta/beta + G a^p2 f1^2 f2^2 / 2, rescaling exponents
     r, s (s - 2r + 3 = 0) and kappa2 = 8 pi G_N / A^2.  dtype is the element
-    type of the lattice arrays (float32 or float64).
+    type of the lattice arrays (float32 or float64).  stencil selects the
+    Laplacian: 7 (6 neighbours) or 27 (the paper's own, Sec. II.C).
     """
 
     def __init__(self, N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float,
                  s: float, kappa2: float, dtype: torch.dtype = torch.float32,
                  device: str | torch.device = "cuda", tile_y: int = 0, zchunk: int = 0,
-                 tile_x: int = 0, stream: torch.cuda.Stream | None = None):
+                 tile_x: int = 0, stream: torch.cuda.Stream | None = None, stencil: int = 7):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.N, self.dtype = int(N), dtype
         self.device = torch.device(device)
         self.params = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1),
                              float(G), float(r), float(s), float(kappa2), int(tile_y), int(zchunk),
-                             int(tile_x), 0)
+                             int(tile_x), int(stencil))
         size = ctypes.c_size_t()
         check(lib().lf_workspace_bytes(ctypes.byref(self.params), ctypes.byref(size)))
         self.ws_bytes = size.value
@@ -217,6 +219,7 @@ class LeapfrogLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, G, f1, f2, v1, v2, spec):
         kw = {k: spec[k] for k in ("N", "L", "dt", "beta", "c1", "r", "s", "kappa2")}
+        kw["stencil"] = spec.get("stencil", 7)
         lat = Lattice(**kw, G=float(G), dtype=spec.get("dtype", torch.float32), device=f1.device)
         lat.init(f1.detach(), f2.detach(), v1.detach(), v2.detach(), spec["a0"], spec["ad0"])
         loss = lat.adjoint_forward(spec["n"], spec["K"], spec.get("weights", (0.0, 1.0, 0.0, 1.0)))
@@ -242,7 +245,8 @@ class Ensemble:
     """R independent lattices stepped together by liblf's batched kernels.
 
     members: list of dicts with the Lattice keyword arguments N, L, dt, beta,
-    c1, G, r, s, kappa2 (dtype and beta common to all)."""
+    c1, G, r, s, kappa2 and optionally stencil (dtype, beta and stencil
+    common to all)."""
 
     def __init__(self, members, dtype: torch.dtype = torch.float32, device="cuda", tile_x: int = 0,
                  tile_y: int = 0, zchunks=None, stream: torch.cuda.Stream | None = None):
@@ -254,7 +258,7 @@ class Ensemble:
             zc = int(zchunks[i]) if zchunks is not None else 0
             arr[i] = Params(int(m["N"]), _DT[dtype], float(m["L"]), float(m["dt"]), int(m["beta"]), 0,
                             float(m["c1"]), float(m["G"]), float(m["r"]), float(m["s"]),
-                            float(m["kappa2"]), int(tile_y), zc, int(tile_x), 0)
+                            float(m["kappa2"]), int(tile_y), zc, int(tile_x), int(m.get("stencil", 7)))
         self.params = arr
         self.Ns = [int(m["N"]) for m in members]
         size = ctypes.c_size_t()

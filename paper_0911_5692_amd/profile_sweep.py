@@ -27,9 +27,11 @@ ROOT = os.path.dirname(PKG)
 COPY_MIB = 1024
 
 
-def sweep_source_hash() -> str:
+def sweep_source_hash(stencil: int = 7) -> str:
+    """Hash of the sources of the sweep kernel of this stencil."""
     h = hashlib.sha256()
-    for f in ("lf_sweep.hip", "lf_internal.h"):
+    main = "lf_sweep27.hip" if stencil == 27 else "lf_sweep.hip"
+    for f in (main, "lf_sweep_common.h", "lf_internal.h", "lf_stencil.h"):
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -105,7 +107,7 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
     kf, kw = copy_bytes / fc, copy_bytes / wc
     fetch = sum(f_sweep) / len(f_sweep) * 1024.0 * kf
     write = sum(w_sweep) / len(w_sweep) * 1024.0 * kw
-    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(), algorithmic_bytes_per_launch=alg,
+    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(w.stencil), algorithmic_bytes_per_launch=alg,
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_calibration=kf, write_calibration=kw,
                fetch_over_algorithmic_reads=fetch / (alg / 2), write_over_algorithmic_writes=write / (alg / 2),

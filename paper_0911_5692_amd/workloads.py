@@ -49,6 +49,7 @@ class Workload:
     steps: int
     dtype: str          # "f32" or "f64": element type of the lattice arrays
     ic: str             # "white" | "grf" | "vacuum"
+    stencil: int = 7    # Laplacian: 7 or 27 points (Sec. II.C)
 
     @property
     def dx(self) -> float:
@@ -61,7 +62,7 @@ class Workload:
     def model(self) -> dict:
         """Keyword arguments accepted by both the Lattice and the oracle Model."""
         return dict(N=self.N, L=self.L, dt=self.dt, beta=self.beta, c1=self.c1, G=self.G,
-                    r=self.r, s=self.s, kappa2=self.kappa2)
+                    r=self.r, s=self.s, kappa2=self.kappa2, stencil=self.stencil)
 
     def resized(self, N: int) -> "Workload":
         """Same model, dx and dt on an N^3 box (L scales with N)."""
@@ -79,6 +80,8 @@ CFG2 = _lphi4("lphi4_256c_f32", 2, 256, 1000, "f32", "grf")
 CFG3 = Workload("m2phi2_512c_f32", 3, 512, 10.0, 2.0 ** -10, 2, 1.0, 2.5e5, 1.5, 0.0, KAPPA2,
                 2000, "f32", "vacuum")
 CFG5 = _lphi4("lphi4_128c_f32_adjoint", 5, 128, 500, "f32", "white")
+# the 512^3 m^2 phi^2 run with the paper's own 27-point Laplacian (same inputs)
+CFG3_S27 = replace(CFG3, name="m2phi2_512c_f32_s27", stencil=27)
 # ensemble: 48 x 64^3 + 16 x 96^3 + 4 x 160^3 of the lambda phi^4 model, own dx and dt each
 ENSEMBLE_SIZES = [64] * 48 + [96] * 16 + [160] * 4
 ENSEMBLE_STEPS = 500
@@ -89,12 +92,13 @@ def ensemble_members():
             for r, n in enumerate(ENSEMBLE_SIZES)]
 
 
-WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5)}
+WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5, CFG3_S27)}
 
 # Sweep launch shapes used by the benchmark, as chosen by lf_autotune on an
 # MI355X (gfx950); re-run the autotuner (bench.py --autotune) on other parts.
 BENCH_SHAPES = {
     CFG3.name: dict(tile_x=128, tile_y=8, zchunk=64),
+    CFG3_S27.name: dict(tile_x=128, tile_y=8, zchunk=64),
 }
 
 

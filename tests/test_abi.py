@@ -43,7 +43,7 @@ def _params(LB, **kw):
 
 def test_abi_version_and_workspace(LB):
     lib = LB.lib()
-    assert lib.lf_abi_version() == 1
+    assert lib.lf_abi_version() == 2
     size = ctypes.c_size_t()
     assert lib.lf_workspace_bytes(ctypes.byref(_params(LB)), ctypes.byref(size)) == 0
     assert size.value >= 8 * 32 ** 3 * 4

@@ -1,0 +1,185 @@
+"""The 27-point Laplacian (Sec. II.C) on the GPU: every sweep variant, the
+energies, rho/p, the ensemble and the adjoint against the FP64 oracle with
+the same stencil, and the exact discrete free wave."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from _parity import ARRAYS, compare_state, gpu_run, log, oracle_run, to_dev
+from paper_0911_5692_amd import Ensemble, Lattice
+from paper_0911_5692_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-10}
+
+
+def _s27(w):
+    return replace(w, stencil=27)
+
+
+def _fields(lat):
+    return [x.cpu().numpy() for x in lat.fields(dtype=torch.float64)]
+
+
+def _check(w, steps, dtype, reps=1, **kw):
+    log(f"[s27] {w.name} N={w.N} reps={reps} steps={steps} {dtype} {kw}")
+    st, en, ad0, ic = oracle_run(w, steps)
+    lat, gad0 = gpu_run(w, ic, steps, dtype=dtype, reps=reps, **kw)
+    assert abs(gad0 - ad0) <= 1e-12 * ad0
+    full = lat.fields(dtype=torch.float64)
+    n = w.N
+    if reps > 1:
+        for k, x in zip(ARRAYS, full):
+            t = x.view(reps, n, reps, n, reps, n)
+            assert bool((t == t[0:1, :, 0:1, :, 0:1, :]).all()), f"periodic copies of {k} differ"
+    errs = compare_state([x[:n, :n, :n].cpu().numpy() for x in full], st)
+    del full
+    g = lat.energies()
+    log(f"[s27]   {errs} a {g['a']} vs {en['a']} R {g['R']} vs {en['R']}")
+    assert max(errs.values()) <= TOL[dtype], errs
+    atol = 1e-12 if dtype == "f64" else 1e-9
+    assert abs(g["a"] - en["a"]) <= atol * en["a"]
+    assert abs(g["ad"] - en["ad"]) <= atol * abs(en["ad"])
+    assert abs(g["R"] - en["R"]) <= (1e-12 if dtype == "f64" else 1e-8)
+    for k in ("K1", "K2", "G1", "G2", "P", "rho"):
+        assert abs(g[k] - en[k]) <= (1e-10 if dtype == "f64" else 1e-5) * abs(en[k]) + 1e-300, k
+    assert g["step"] == steps
+    return lat
+
+
+@pytest.mark.parametrize("tile_x,tile_y,zchunk", [(0, 1, 0), (64, 4, 13), (64, 8, 16), (64, 16, 7),
+                                                  (128, 4, 9), (128, 8, 0)])
+def test_sweep_variants_fp32(tile_x, tile_y, zchunk):
+    """Plain and every LDS tile (ragged: 48 = 0.75 x 64, 0.375 x 128) against
+    the oracle, lambda phi^4 recipe, 150 steps."""
+    _check(_s27(W.CFG2).resized(48), 150, "f32", tile_x=tile_x, tile_y=tile_y, zchunk=zchunk)
+
+
+@pytest.mark.parametrize("tile_x,tile_y", [(0, 1), (64, 8), (64, 16), (128, 8)])
+def test_sweep_variants_fp64(tile_x, tile_y):
+    _check(_s27(W.CFG1).resized(40), 60, "f64", tile_x=tile_x, tile_y=tile_y,
+           zchunk=16 if tile_y > 1 else 0)
+
+
+@pytest.mark.parametrize("N", [4, 5, 7, 33])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_edge_and_ragged_sizes(N, dtype):
+    _check(_s27(W.CFG1).resized(N), 40, dtype)
+
+
+def test_m2phi2_recipe_64_fp32_2000_steps():
+    _check(_s27(W.CFG3).resized(64), 2000, "f32")
+
+
+def test_full_size_512_periodic_tiles():
+    """512^3 FP32 in the benchmark's launch shape (64^3-periodic initial
+    state): every periodic copy bitwise equal, and equal to the oracle's 64^3
+    evolution, after 400 steps."""
+    w = W.CFG3_S27.resized(64)
+    _check(w, 400, "f32", reps=8, **W.BENCH_SHAPES[W.CFG3_S27.name])
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_free_wave_exact_discrete_solution(dtype, tol):
+    """kappa^2 = 0, G = 0, V = c1 f^2/2: cos(k.x) evolves as cos(k Omega dt)
+    with sin(Omega dt/2) = omega dt/2, omega^2 = -lambda_27(k) + c1."""
+    N, dx, dt, c1 = 32, 0.5, 0.05, 2.5
+    lat = Lattice(N=N, L=N * dx, dt=dt, beta=2, c1=c1, G=0.0, r=1.5, s=0.0, kappa2=0.0, stencil=27,
+                  dtype=torch.float64 if dtype == "f64" else torch.float32)
+    z, y, x = np.meshgrid(*(np.arange(N) * dx,) * 3, indexing="ij")
+    n = np.array([3, 5, 16])
+    k = 2 * np.pi * n / (N * dx)
+    shape = np.cos(k[0] * x + k[1] * y + k[2] * z)
+    zero = np.zeros_like(shape)
+    lat.init(to_dev(shape), to_dev(zero), to_dev(zero), to_dev(zero), 1.0, 0.0)
+    steps = 300
+    lat.step(steps)
+    c = np.cos(k * dx)
+    lam = (-64 / 15 + 14 / 15 * c.sum() + 0.4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2])
+           + 4 / 15 * c.prod()) / dx ** 2
+    Om = 2 * np.arcsin(np.sqrt(c1 - lam) * dt / 2) / dt
+    f1 = lat.fields(synchronized=True, dtype=torch.float64)[0].cpu().numpy()
+    assert np.max(np.abs(f1 - np.cos(steps * Om * dt) * shape)) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_rho_p_matches_oracle(dtype, tol):
+    w = _s27(W.CFG3).resized(40)
+    st, _, _, ic = oracle_run(w, 120)
+    rho, p, avg = O.rho_p(st)
+    lat, _ = gpu_run(w, ic, 120, dtype=dtype)
+    grho, gp, gavg = lat.rho_p()
+    assert float(np.max(np.abs(grho.cpu().numpy() - rho)) / np.max(np.abs(rho))) <= tol
+    assert float(np.max(np.abs(gp.cpu().numpy() - p)) / np.max(np.abs(p))) <= tol
+    for k in ("rho", "p", "w"):
+        assert abs(gavg[k] - avg[k]) <= tol * abs(avg[k]), k
+
+
+def test_deterministic_repeat_bitwise():
+    w = _s27(W.CFG3).resized(64)
+    ic = W.make_inputs(w)
+    outs = []
+    for _ in range(2):
+        lat, _ = gpu_run(w, ic, 60)
+        outs.append((lat.get_state()[0], lat.energies()))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert torch.equal(a, b)
+    assert outs[0][1] == outs[1][1]
+
+
+def test_ensemble_matches_oracle_and_single_lattice():
+    """Mixed sizes in one persistent launch per step: each realization against
+    the oracle, and bitwise against a lone lattice with the same tile and
+    z-chunk."""
+    members = [_s27(W.CFG1).resized(n) for n in (16, 24, 33, 40)]
+    ens = Ensemble([m.model() for m in members], dtype=torch.float32, tile_x=64, tile_y=8,
+                   zchunks=[16] * len(members))
+    for r, m in enumerate(members):
+        ic = W.make_inputs(m, realization=r)
+        ens.init_physical(r, *(to_dev(ic[k]) for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+    steps = 70
+    ens.step(steps)
+    en = ens.energies()
+    for r, m in enumerate(members):
+        st, oe, _, ic = oracle_run(m, steps, realization=r)
+        errs = compare_state([x.cpu().numpy() for x in ens.fields(r)], st)
+        log(f"[s27 ens] r={r} N={m.N} {errs}")
+        assert max(errs.values()) <= 1e-5, (r, errs)
+        assert abs(en[r]["a"] - oe["a"]) <= 1e-9 * oe["a"]
+        lat = Lattice(**m.model(), dtype=torch.float32, tile_x=64, tile_y=8, zchunk=16)
+        lat.init_physical(*(to_dev(ic[k]) for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+        lat.step(steps)
+        for x, y in zip(ens.fields(r), lat.fields()):
+            assert torch.equal(x, y), r
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
+def test_adjoint_matches_oracle_adjoint(dtype, tol):
+    N = 10
+    m = O.Model(N=N, L=N * 0.625, dt=0.03125, beta=4, c1=1.0, G=100.0, r=1.0, s=-1.0, kappa2=1.0187733,
+                stencil=27)
+    rng = np.random.default_rng(3)
+    f1 = 1.0 + 0.05 * rng.standard_normal((N, N, N))
+    f2 = 0.05 * rng.standard_normal((N, N, N))
+    u1 = -0.3 + 0.05 * rng.standard_normal((N, N, N))
+    u2 = 0.05 * rng.standard_normal((N, N, N))
+    v1, v2, ad0 = O.init_physical(m, f1, f2, u1, u2, 1.0)
+    weights = (0.0, 1.0, 0.0, 1.0)
+    n, K = 30, 7
+    ref = O.adjoint(m, f1, f2, v1, v2, 1.0, ad0, n, wK=weights[:2], wG=weights[2:])
+    lat = Lattice(N=N, L=m.L, dt=m.dt, beta=4, c1=1.0, G=m.G, r=1.0, s=-1.0, kappa2=m.kappa2,
+                  dtype=dtype, stencil=27)
+    lat.init(to_dev(f1), to_dev(f2), to_dev(v1), to_dev(v2), 1.0, ad0)
+    loss = lat.adjoint_forward(n, K, weights)
+    g = lat.adjoint_backward(1.0)
+    log(f"[s27 adj] {dtype}: loss {loss} vs {ref['E']}; dG {g['G']} vs {ref['dG']}")
+    assert abs(loss - ref["E"]) <= tol * abs(ref["E"])
+    assert abs(g["G"] - ref["dG"]) <= tol * abs(ref["dG"])
+    assert abs(g["a0"] - ref["da0"]) <= tol * abs(ref["da0"])
+    for k in ("f1", "f2", "v1", "v2"):
+        err = float(np.max(np.abs(g[k].cpu().numpy() - ref[k])) / np.max(np.abs(ref[k])))
+        assert err <= tol, (k, err)
