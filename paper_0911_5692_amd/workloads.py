@@ -98,7 +98,7 @@ WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5, CFG3_S27)}
 # MI355X (gfx950); re-run the autotuner (bench.py --autotune) on other parts.
 BENCH_SHAPES = {
     CFG3.name: dict(tile_x=128, tile_y=8, zchunk=64),
-    CFG3_S27.name: dict(tile_x=128, tile_y=8, zchunk=64),
+    CFG3_S27.name: dict(tile_x=64, tile_y=8, zchunk=64),
 }
 
 
