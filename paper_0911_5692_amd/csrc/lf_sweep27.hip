@@ -42,6 +42,19 @@ namespace lf {
 
 namespace {
 
+// Element at a 32-bit unsigned byte offset from a uniform base: lets the
+// compiler address global memory as SGPR base + VGPR offset.
+template <typename T>
+__device__ inline T ld_at(const T *base, unsigned boff)
+{
+    return *(const T *)((const char *)base + boff);
+}
+template <typename T>
+__device__ inline void st_nt(T v, T *base, unsigned boff)
+{
+    __builtin_nontemporal_store(v, (T *)((char *)base + boff));
+}
+
 // One block's work: tile (x0, y0) of an N^3 lattice over planes [z0, z1),
 // writing its four partial sums to part_row[0..3].
 template <typename T, int NH, int TX, int TY>
@@ -75,8 +88,15 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     const int wv = min(TX, N - x0), hv = min(TY, N - y0);  // valid interior extent
 
     // interior sites (x0 + t % TX, y0 + t / TX + RPR k)
-    int goff[KI], lsd[KI], lsn[KI];
-    bool act[KI], okx[KI], oky[KI], ok4[KI];
+    unsigned goff[KI];  // byte offsets within a plane
+    int lsd[KI], lsn[KI];
+    bool act[KI];
+    // bonds that may leave the interior and ring: (+1,-1) in planes z and
+    // z-1, (+1,0), (0,+1), (-1,+1), (+1,+1) in plane z-1.  Index of the
+    // neighbour's slot, or of the site's own slot when the bond is not this
+    // block's, and a 0/1 multiplier of the difference
+    int ix4[KI], ixx[KI], ixy[KI], ixyl[KI], ixxy[KI];
+    T m4[KI], mx[KI], my[KI], mxy[KI];
     const int cx = t % TX, cy = t / TX;
     const int xi = x0 + cx;
 #pragma unroll
@@ -84,45 +104,58 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         const int yl = cy + RPR * k;
         const int y = y0 + yl;
         act[k] = (xi < N) && (y < N);
-        goff[k] = (y % N) * N + (xi % N);  // in-bounds even when inactive
+        goff[k] = (unsigned)((y % N) * N + (xi % N)) * sizeof(T);  // in-bounds even when inactive
         lsd[k] = (yl + 2) * LW + cx + 2;
         lsn[k] = (yl + 1) * NW + cx + 1;
-        okx[k] = cx + 1 < wv;              // (cx+1, yl) is interior
-        oky[k] = yl + 1 < hv;              // (cx, yl+1) is interior
-        ok4[k] = (yl == 0) || okx[k];      // (cx+1, yl-1) is interior or ring
+        const bool okx = cx + 1 < wv;        // (cx+1, yl) is interior
+        const bool oky = yl + 1 < hv;        // (cx, yl+1) is interior
+        const bool ok4 = (yl == 0) || okx;   // (cx+1, yl-1) is interior or ring
+        const int l = lsn[k];
+        ix4[k] = ok4 ? l - NW + 1 : l;
+        ixx[k] = okx ? l + 1 : l;
+        ixy[k] = oky ? l + NW : l;
+        ixyl[k] = oky ? l + NW - 1 : l;
+        ixxy[k] = (okx && oky) ? l + NW + 1 : l;
+        m4[k] = ok4 ? T(1) : T(0);
+        mx[k] = okx ? T(1) : T(0);
+        my[k] = oky ? T(1) : T(0);
+        mxy[k] = (okx && oky) ? T(1) : T(0);
     }
     // ring site of this thread (t < NRING): new value only, never stored
     const bool hasr = t < NRING;
     const bool rrow = t < TX + 2;
     const int rlx = rrow ? t - 1 : -1, rly = rrow ? -1 : t - (TX + 2);
-    const int roff = hasr ? wrapc(y0 + rly) * N + wrapc(x0 + rlx) : 0;
+    const unsigned roff = hasr ? (unsigned)(wrapc(y0 + rly) * N + wrapc(x0 + rlx)) * sizeof(T) : 0u;
     const int rlsd = hasr ? (rly + 2) * LW + rlx + 2 : 0;
     const int rlsn = hasr ? (rly + 1) * NW + rlx + 1 : 0;
     // the ring's bonds into the interior: three to plane z-1 (index rq,
     // validity rv; the middle one an edge, the outer two corners) and, for
     // the ring column, one in-plane edge (rqi, rvi)
     int rq[3], rqi = rlsn;
-    bool rv[3], rvi = false;
+    T rv[3], rvi = T(0);  // 0/1 multipliers
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
+        bool ok;
         if (rrow) {
             const int x = rlx + j - 1;  // interior (x, 0)
-            rv[j] = hasr && x >= 0 && x < wv;
-            rq[j] = rv[j] ? NW + x + 1 : rlsn;
+            ok = hasr && x >= 0 && x < wv;
+            rq[j] = ok ? NW + x + 1 : rlsn;
         } else {
             const int y = rly + j - 1;  // interior (0, y)
-            rv[j] = hasr && rly < hv && y >= 0 && y < hv;
-            rq[j] = rv[j] ? (y + 1) * NW + 1 : rlsn;
+            ok = hasr && rly < hv && y >= 0 && y < hv;
+            rq[j] = ok ? (y + 1) * NW + 1 : rlsn;
         }
+        rv[j] = ok ? T(1) : T(0);
     }
     if (hasr && !rrow && rly >= 1 && rly < hv) {
-        rvi = true;
+        rvi = T(1);
         rqi = rly * NW + 1;  // interior (0, rly - 1)
     }
     // halo cells of this thread (t and t + 256 below NHALO): staged-plane
     // border that no computed site covers
     bool hash[2];
-    int hoff[2], hlsd[2];
+    unsigned hoff[2];
+    int hlsd[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int hc = t + 256 * m;
@@ -134,7 +167,7 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         else if (hc < 2 * (TX + 4) + 2 * (TY + 1)) { hlx = TX + 1; hly = hc - 2 * (TX + 4) - (TY + 1) - 1; }
         else { hlx = TX; hly = hc - 2 * (TX + 4) - 2 * (TY + 1); }
         if (!hash[m]) { hlx = 0; hly = 0; }
-        hoff[m] = wrapc(y0 + hly) * N + wrapc(x0 + hlx);
+        hoff[m] = (unsigned)(wrapc(y0 + hly) * N + wrapc(x0 + hlx)) * sizeof(T);
         hlsd[m] = (hly + 2) * LW + hlx + 2;
     }
     // plane base pointers: z stays within [z0 - 3, z1 + 2], one wrap suffices
@@ -158,26 +191,26 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         const T *b1 = plane(d1, z0 - 1), *b2 = plane(d2, z0 - 1);
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
-            qp1[k] = a1[goff[k]]; qp2[k] = a2[goff[k]];
-            nd1[k] = b1[goff[k]]; nd2[k] = b2[goff[k]];
+            qp1[k] = ld_at(a1, goff[k]); qp2[k] = ld_at(a2, goff[k]);
+            nd1[k] = ld_at(b1, goff[k]); nd2[k] = ld_at(b2, goff[k]);
             qc1[k] = 0; qc2[k] = 0; ev1[k] = 0; ev2[k] = 0;
             am1[k] = 0; am2[k] = 0; ac1[k] = 0; ac2[k] = 0; bc1[k] = 0; bc2[k] = 0;
             sd[0][0][lsd[k]] = qp1[k];
             sd[0][1][lsd[k]] = qp2[k];
         }
         if (hasr) {
-            rqp1 = a1[roff]; rqp2 = a2[roff];
-            rnd1 = b1[roff]; rnd2 = b2[roff];
+            rqp1 = ld_at(a1, roff); rqp2 = ld_at(a2, roff);
+            rnd1 = ld_at(b1, roff); rnd2 = ld_at(b2, roff);
             sd[0][0][rlsd] = rqp1;
             sd[0][1][rlsd] = rqp2;
         }
 #pragma unroll
         for (int m = 0; m < 2; ++m)
             if (hash[m]) {
-                sd[0][0][hlsd[m]] = a1[hoff[m]];
-                sd[0][1][hlsd[m]] = a2[hoff[m]];
-                hv1[m] = b1[hoff[m]];
-                hv2[m] = b2[hoff[m]];
+                sd[0][0][hlsd[m]] = ld_at(a1, hoff[m]);
+                sd[0][1][hlsd[m]] = ld_at(a2, hoff[m]);
+                hv1[m] = ld_at(b1, hoff[m]);
+                hv2[m] = ld_at(b2, hoff[m]);
             }
         __syncthreads();
     }
@@ -194,24 +227,23 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             const T *b1 = plane(e1, z + 1), *b2 = plane(e2, z + 1);
 #pragma unroll
             for (int k = 0; k < KI; ++k) {
-                ld1[k] = need_d ? a1[goff[k]] : T(0);
-                ld2[k] = need_d ? a2[goff[k]] : T(0);
-                le1[k] = need_e ? b1[goff[k]] : T(0);
-                le2[k] = need_e ? b2[goff[k]] : T(0);
+                ld1[k] = need_d ? ld_at(a1, goff[k]) : T(0);
+                ld2[k] = need_d ? ld_at(a2, goff[k]) : T(0);
+                le1[k] = need_e ? ld_at(b1, goff[k]) : T(0);
+                le2[k] = need_e ? ld_at(b2, goff[k]) : T(0);
             }
-            rld1 = (hasr && need_d) ? a1[roff] : T(0);
-            rld2 = (hasr && need_d) ? a2[roff] : T(0);
-            rle1 = (hasr && need_e) ? b1[roff] : T(0);
-            rle2 = (hasr && need_e) ? b2[roff] : T(0);
+            rld1 = (hasr && need_d) ? ld_at(a1, roff) : T(0);
+            rld2 = (hasr && need_d) ? ld_at(a2, roff) : T(0);
+            rle1 = (hasr && need_e) ? ld_at(b1, roff) : T(0);
+            rle2 = (hasr && need_e) ? ld_at(b2, roff) : T(0);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                lh1[m] = (hash[m] && need_d) ? a1[hoff[m]] : T(0);
-                lh2[m] = (hash[m] && need_d) ? a2[hoff[m]] : T(0);
+                lh1[m] = (hash[m] && need_d) ? ld_at(a1, hoff[m]) : T(0);
+                lh2[m] = (hash[m] && need_d) ? ld_at(a2, hoff[m]) : T(0);
             }
         }
 
-        const bool upd = z >= z0 - 1;  // plane z is updated (z0-1: ring only for the reductions)
-        const bool live = z >= z0;     // plane z is stored and reduced
+        const bool live = z >= z0;  // plane z is stored and reduced (z0-1 only feeds the reductions)
         const T *s0 = sd[cur][0], *s1 = sd[cur][1];
         T *n0 = sn[nb_cur][0], *n1 = sn[nb_cur][1];
         T an1[KI], an2[KI], bn1[KI], bn2[KI], na1[KI], na2[KI];
@@ -236,15 +268,15 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
                 T *o_e1 = const_cast<T *>(plane(e1n, z)), *o_e2 = const_cast<T *>(plane(e2n, z));
                 T *o_d1 = const_cast<T *>(plane(d1n, z)), *o_d2 = const_cast<T *>(plane(d2n, z));
                 // streamed once: non-temporal, so L2 keeps the halo rows instead
-                __builtin_nontemporal_store(ea, o_e1 + goff[k]);
-                __builtin_nontemporal_store(eb, o_e2 + goff[k]);
-                __builtin_nontemporal_store(na1[k], o_d1 + goff[k]);
-                __builtin_nontemporal_store(na2[k], o_d2 + goff[k]);
+                st_nt(ea, o_e1, goff[k]);
+                st_nt(eb, o_e2, goff[k]);
+                st_nt(na1[k], o_d1, goff[k]);
+                st_nt(na2[k], o_d2, goff[k]);
             }
-            if (upd) {
-                n0[lsn[k]] = na1[k];
-                n1[lsn[k]] = na2[k];
-            }
+            // planes below z0-1 are written too: their slots are rewritten
+            // before the first read
+            n0[lsn[k]] = na1[k];
+            n1[lsn[k]] = na2[k];
         }
         T rna1 = 0, rna2 = 0, ran1 = 0, ran2 = 0, rbn1 = 0, rbn2 = 0;
         if (hasr) {
@@ -261,13 +293,12 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             c.force(rqc1, rqc2, (rbc1 + ram1) + ran1, (rbc2 + ram2) + ran2, ia, ib);
             rna1 = rqc1 + c.dt * (rev1 + ia);
             rna2 = rqc2 + c.dt * (rev2 + ib);
-            if (upd) {
-                n0[rlsn] = rna1;
-                n1[rlsn] = rna2;
-            }
+            n0[rlsn] = rna1;
+            n1[rlsn] = rna2;
         }
-        // stage plane z+2 into the other buffer (loaded one iteration ago)
-        if (z + 2 <= z1) {
+        // stage plane z+2 into the other buffer (loaded one iteration ago;
+        // past z1 the registers hold zeros and the buffer is not read again)
+        {
             T *t0 = sd[cur ^ 1][0], *t1 = sd[cur ^ 1][1];
 #pragma unroll
             for (int k = 0; k < KI; ++k) { t0[lsd[k]] = nd1[k]; t1[lsd[k]] = nd2[k]; }
@@ -281,19 +312,17 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         if (live) {
             const T *p0 = sn[nb_cur][0], *p1 = sn[nb_cur][1];      // plane z
             const T *m0 = sn[nb_prev][0], *m1 = sn[nb_prev][1];    // plane z-1
-            // bonds of interior site k; a bond to a position outside the
-            // interior and ring reads the site itself (index l) and adds 0
+            // bonds of interior site k; a bond that is not this block's
+            // reads the site's own slot and is multiplied by 0 (no branch)
             auto bonds = [&](const T *P, const T *M, const int l, const T v, const int k) {
                 auto sq = [&](T u) { const T d = v - u; return d * d; };
-                const bool oxy = okx[k] && oky[k];
+                auto sqm = [&](T u, T msk) { const T d = (v - u) * msk; return d * d; };
                 const T F = (sq(P[l - 1]) + sq(P[l - NW])) + sq(M[l]);
-                T E = sq(P[l - NW - 1]) + (ok4[k] ? sq(P[ok4[k] ? l - NW + 1 : l]) : T(0));
+                T E = sq(P[l - NW - 1]) + sqm(P[ix4[k]], m4[k]);
                 E += sq(M[l - 1]) + sq(M[l - NW]);
-                E += okx[k] ? sq(M[okx[k] ? l + 1 : l]) : T(0);
-                E += oky[k] ? sq(M[oky[k] ? l + NW : l]) : T(0);
-                T Cn = sq(M[l - NW - 1]) + (ok4[k] ? sq(M[ok4[k] ? l - NW + 1 : l]) : T(0));
-                Cn += oky[k] ? sq(M[oky[k] ? l + NW - 1 : l]) : T(0);
-                Cn += oxy ? sq(M[oxy ? l + NW + 1 : l]) : T(0);
+                E += sqm(M[ixx[k]], mx[k]) + sqm(M[ixy[k]], my[k]);
+                T Cn = sq(M[l - NW - 1]) + sqm(M[ix4[k]], m4[k]);
+                Cn += sqm(M[ixyl[k]], my[k]) + sqm(M[ixxy[k]], mxy[k]);
                 return (double)((T(14) * F + T(3) * E) + Cn);
             };
 #pragma unroll
@@ -307,10 +336,12 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
                 acc3 += x1 * x1 * x2 * x2;
             }
             if (hasr) {
+                // bonds that are not this block's read the ring's own slot
+                // (rq, rqi = rlsn) and are multiplied by 0
                 auto rb = [&](const T *P, const T *M, const T v) {
-                    auto sq = [&](T u) { const T d = v - u; return d * d; };
-                    const T E = (rv[1] ? sq(M[rq[1]]) : T(0)) + (rvi ? sq(P[rqi]) : T(0));
-                    const T Cn = (rv[0] ? sq(M[rq[0]]) : T(0)) + (rv[2] ? sq(M[rq[2]]) : T(0));
+                    auto sqm = [&](T u, T msk) { const T d = (v - u) * msk; return d * d; };
+                    const T E = sqm(M[rq[1]], rv[1]) + sqm(P[rqi], rvi);
+                    const T Cn = sqm(M[rq[0]], rv[0]) + sqm(M[rq[2]], rv[2]);
                     return (double)(T(3) * E + Cn);
                 };
                 acc0 += rb(p0, m0, rna1);
@@ -360,14 +391,17 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
 }  // namespace
 
 // Waves per SIMD to compile for: as many blocks as the LDS of a CU (160 KB)
-// holds, each block one wave per SIMD, at most 3 in FP32 (168 VGPRs) and 2 in
-// FP64 (which needs more registers).
+// holds, each block one wave per SIMD, at most LF_SWEEP27_MIN_WAVES in FP32
+// and 2 in FP64 (which needs more registers).
+#ifndef LF_SWEEP27_MIN_WAVES
+#define LF_SWEEP27_MIN_WAVES 3
+#endif
 template <typename T, int TX, int TY>
 constexpr int sweep27_waves()
 {
     constexpr int lds = (int)sizeof(T) * (2 * 2 * (TY + 3) * (TX + 4) + 3 * 2 * (TY + 1) * (TX + 2));
     constexpr int by_lds = 160 * 1024 / lds;
-    constexpr int by_regs = sizeof(T) == 4 ? 3 : 2;
+    constexpr int by_regs = sizeof(T) == 4 ? LF_SWEEP27_MIN_WAVES : 2;
     return by_lds < by_regs ? (by_lds < 1 ? 1 : by_lds) : by_regs;
 }
 #define LF_SWEEP27_WAVES(T) (sweep27_waves<T, TX, TY>())
