@@ -64,6 +64,28 @@ def cpu_baseline(w, ic) -> dict:
             "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
 
 
+def time_device_init(w, dtype) -> dict:
+    """Wall time of the on-device vacuum initialisation (noise, FFTs, filter,
+    Friedmann initialisation) at the workload's size: first call (FFT plan
+    setup included) and a second one."""
+    import torch
+
+    from paper_0911_5692_amd import Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    spec = W.vacuum_spec(w, seed=w.cfg)
+    lat = Lattice(**w.model(), dtype=dtype, device="cuda:0")
+    out = {}
+    for key in ("first_ms", "warm_ms"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.init_vacuum(spec, 1.0)
+        torch.cuda.synchronize()
+        out[key] = round((time.perf_counter() - t0) * 1e3, 2)
+    lat.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +95,8 @@ def main() -> int:
     ap.add_argument("--kernel-steps", type=int, default=50,
                     help="eager steps timed per kernel with HIP events (roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-init-timing", action="store_true",
+                    help="skip timing the on-device vacuum initialisation")
     ap.add_argument("--autotune", action="store_true",
                     help="re-run the launch-shape autotuner instead of the committed shape")
     args = ap.parse_args()
@@ -93,7 +117,8 @@ def main() -> int:
     log(f"workload {w.name}: N={w.N} dtype={w.dtype}; generating seeded inputs")
     t0 = time.perf_counter()
     ic = W.make_inputs(w)
-    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+    host_inputs_s = time.perf_counter() - t0
+    log(f"inputs ready in {host_inputs_s:.1f} s")
 
     shape = dict(W.BENCH_SHAPES.get(w.name, {}))
     if args.autotune:
@@ -134,6 +159,12 @@ def main() -> int:
     lat.close()
     torch.cuda.synchronize()
 
+    init = None
+    if not args.no_init_timing:
+        init = time_device_init(w, dtype)
+        init["host_generator_s"] = round(host_inputs_s, 2)
+        log(f"device vacuum initialisation: {init}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
@@ -166,6 +197,7 @@ def main() -> int:
                      else "k_sweep_lds (fused kick-drift, 7-point)",
                      "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
+        "init": init,
     }
     print(json.dumps(line), flush=True)
     return 0

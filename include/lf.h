@@ -286,6 +286,51 @@ int lf_ens_get_fields(lf_ens *ens, int r, void *f1, void *f2, void *v1, void *v2
  *   (0 when the sweep computes it in-sweep).  Blocking.  Advances the state. */
 int lf_time_kernels(lf_ctx *ctx, int64_t n, double *ms, int n_out);
 
+/* ---- vacuum initial state on the device (Sec. II.B) --------------------
+ * The homogeneous values are inputs; the fluctuations are generated through
+ * an FFT, as the paper does after DEFROST (hipFFT in place of CUFFT):
+ *   f_i = f0_i + F_i,  u_i = u0_i + U_i  (program units; u are the rescaled
+ *   physical velocities that lf_init_physical takes),
+ * with F_i, U_i independent Gaussian random fields of power spectrum
+ *   P_F(k) = eps2 / (2 omega_k),  P_U(k) = eps2 omega_k / 2,
+ *   omega_k = sqrt(k^2 + m2_i),  k = 2 pi |n| / L,
+ * n the integer wavevector, zero at n = 0 and for |n| > cutoff.  Lattice
+ * normalisation: unit white noise w filtered as IFFT(FFT(w) sqrt(N^3 P/L^3)),
+ * so <F^2> = sum_k P(k) / L^3.  White noise: Philox4x32-10 (Salmon et al.,
+ * SC'11), counter (i mod 2^32, i div 2^32, j, 0) for site i (x fastest) of
+ * array j = 0..3 (F1, F2, U1, U2), key (seed mod 2^32, seed div 2^32); the
+ * output words x0..x3 give U1 = (x0 2^21 + x1 div 2^11 + 1) 2^-53,
+ * U2 = (x2 2^21 + x3 div 2^11 + 1) 2^-53 and the normal
+ * sqrt(-2 ln U1) cos(2 pi U2).  FP64 throughout. */
+typedef struct lf_vacuum {
+    double f0[2];     /* homogeneous program-unit fields f1, f2 */
+    double u0[2];     /* homogeneous rescaled velocities u1, u2 */
+    double m2[2];     /* m_i^2 of each field's omega_k; m2_i + (2 pi / L)^2 > 0 */
+    double eps2;      /* amplitude^2 of the spectra, >= 0 */
+    double cutoff;    /* largest |n| kept; 0 = N/4 */
+    uint64_t seed;    /* generator key */
+} lf_vacuum;
+
+/* Scratch for lf_vacuum_fields: the half spectrum of one array
+ * (N^2 (N/2+1) complex doubles) plus the FFT work area.  Needs a device (the
+ * FFT plans are created to size their work area). */
+int lf_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes);
+/* Generate f1, f2, u1, u2 (FP64 device arrays of N^3, 256-byte aligned,
+ * caller-owned) for the lattice of p on `stream`.  The large buffers come
+ * from `workspace`; hipFFT's plans keep small tables of their own for the
+ * duration of the call.  Blocking; same seed, N and spectrum give bitwise
+ * the same arrays. */
+int lf_vacuum_fields(const lf_params *p, const lf_vacuum *v, void *stream, void *workspace,
+                     size_t ws_bytes, double *f1, double *f2, double *u1, double *u2);
+/* Scratch for lf_init_vacuum: four FP64 arrays of N^3 plus
+ * lf_vacuum_workspace_bytes. */
+int lf_init_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes);
+/* Generate a vacuum state in `workspace` and initialise the context from it
+ * as lf_init_physical does (Friedmann a'_0 returned in *ad0_out).  Blocking;
+ * the workspace may be reused after the call. */
+int lf_init_vacuum(lf_ctx *ctx, const lf_vacuum *v, double a0, void *workspace, size_t ws_bytes,
+                   double *ad0_out);
+
 #ifdef __cplusplus
 }
 #endif

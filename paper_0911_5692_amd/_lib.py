@@ -47,6 +47,11 @@ class Scalars(ctypes.Structure):
                 ("pad_", ctypes.c_uint32)]
 
 
+class Vacuum(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double * 2), ("u0", ctypes.c_double * 2), ("m2", ctypes.c_double * 2),
+                ("eps2", ctypes.c_double), ("cutoff", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -93,6 +98,12 @@ SIGNATURES = {
     "lf_ens_last_step_ms": ([_vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "lf_ens_energies": ([_vp, ctypes.POINTER(Report)], ctypes.c_int),
     "lf_ens_get_fields": ([_vp, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "lf_vacuum_workspace_bytes": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lf_vacuum_fields": ([ctypes.POINTER(Params), ctypes.POINTER(Vacuum), _vp, _vp, ctypes.c_size_t, _vp, _vp,
+                          _vp, _vp], ctypes.c_int),
+    "lf_init_vacuum_workspace_bytes": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lf_init_vacuum": ([_vp, ctypes.POINTER(Vacuum), ctypes.c_double, _vp, ctypes.c_size_t,
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
 }
 
 

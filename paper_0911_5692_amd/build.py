@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblf.so")
-SOURCES = ["lf_api.hip", "lf_kernels.hip", "lf_sweep.hip", "lf_sweep27.hip", "lf_adjoint.hip"]
+SOURCES = ["lf_api.hip", "lf_kernels.hip", "lf_sweep.hip", "lf_sweep27.hip", "lf_adjoint.hip", "lf_vacuum.hip"]
+LIBS = ["-L/opt/rocm/lib", "-lhipfft"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -38,7 +39,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp], check=True)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

@@ -759,6 +759,82 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- vacuum initial state
+
+namespace {
+
+int validate_vacuum(const lf_params *p, const lf_vacuum *v)
+{
+    if (!v) return fail(LF_EINVAL, "vacuum spec is NULL");
+    const double kmin2 = (2.0 * M_PI / p->L) * (2.0 * M_PI / p->L);
+    for (int i = 0; i < 2; ++i) {
+        if (!isfinite(v->f0[i]) || !isfinite(v->u0[i]) || !isfinite(v->m2[i]))
+            return fail(LF_EINVAL, "vacuum spec: non-finite homogeneous value or m2");
+        if (!(v->m2[i] + kmin2 > 0.0))
+            return fail(LF_EINVAL, "vacuum spec: m2[%d] = %g leaves omega_k imaginary", i, v->m2[i]);
+    }
+    if (!(v->eps2 >= 0.0) || !isfinite(v->eps2)) return fail(LF_EINVAL, "vacuum spec: eps2 must be >= 0");
+    if (!(v->cutoff >= 0.0) || !isfinite(v->cutoff)) return fail(LF_EINVAL, "vacuum spec: cutoff must be >= 0");
+    return LF_OK;
+}
+
+size_t vac_array_bytes(int N) { return align_up((size_t)N * N * N * sizeof(double)); }
+
+}  // namespace
+
+extern "C" {
+
+int lf_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    char msg[256];
+    if (vacuum_workspace(p->N, out_bytes, msg, sizeof msg)) return fail(LF_EHIP, "%s", msg);
+    return LF_OK;
+}
+
+int lf_vacuum_fields(const lf_params *p, const lf_vacuum *v, void *stream, void *workspace, size_t ws_bytes,
+                     double *f1, double *f2, double *u1, double *u2)
+{
+    int rc = validate(p);
+    if (rc || (rc = validate_vacuum(p, v))) return rc;
+    if ((rc = check_ptr(workspace, "workspace")) || (rc = check_ptr(f1, "f1")) || (rc = check_ptr(f2, "f2")) ||
+        (rc = check_ptr(u1, "u1")) || (rc = check_ptr(u2, "u2")))
+        return rc;
+    double *const out[4] = {f1, f2, u1, u2};
+    char msg[256];
+    const int e = vacuum_generate(p->N, p->L, v, (hipStream_t)stream, workspace, ws_bytes, out, msg, sizeof msg);
+    if (e) return fail(e == 2 ? LF_ENOMEM : LF_EHIP, "%s", msg);
+    return LF_OK;
+}
+
+int lf_init_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes)
+{
+    int rc = lf_vacuum_workspace_bytes(p, out_bytes);
+    if (rc) return rc;
+    *out_bytes += 4 * vac_array_bytes(p->N);
+    return LF_OK;
+}
+
+int lf_init_vacuum(lf_ctx *c, const lf_vacuum *v, double a0, void *workspace, size_t ws_bytes, double *ad0_out)
+{
+    if (!c) return fail(LF_EINVAL, "ctx is NULL");
+    if (!ad0_out) return fail(LF_EINVAL, "ad0_out is NULL");
+    int rc;
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+    const size_t arr = vac_array_bytes(c->p.N);
+    if (ws_bytes < 4 * arr) return fail(LF_ENOMEM, "workspace of %zu bytes is smaller than four arrays", ws_bytes);
+    char *w = (char *)workspace;
+    double *f[4] = {(double *)w, (double *)(w + arr), (double *)(w + 2 * arr), (double *)(w + 3 * arr)};
+    if ((rc = lf_vacuum_fields(&c->p, v, (void *)c->stream, w + 4 * arr, ws_bytes - 4 * arr, f[0], f[1], f[2],
+                               f[3])))
+        return rc;
+    return lf_init_physical(c, f[0], f[1], f[2], f[3], LF_F64, a0, ad0_out);
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- autotuner
 
 namespace {

@@ -124,5 +124,14 @@ void launch_adj_step(int stencil, int dtype, const void *d1, const void *d2, int
                      double *part, int nblk, double *A, double *cf, hipStream_t st);
 void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStream_t st);
 void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st);
+}  // namespace lf
+
+// vacuum initial state (lf_vacuum.hip); nonzero return = failure, message in msg
+struct lf_vacuum;
+namespace lf {
+size_t vacuum_spectrum_bytes(int N);
+int vacuum_workspace(int N, size_t *bytes, char *msg, size_t len);
+int vacuum_generate(int N, double L, const struct ::lf_vacuum *v, hipStream_t st, void *ws, size_t ws_bytes,
+                    double *const out[4], char *msg, size_t len);
 
 }  // namespace lf

@@ -10,7 +10,7 @@ import os
 
 import torch
 
-from ._lib import LF_F32, LF_F64, Params, Report, Scalars, check, lib
+from ._lib import LF_F32, LF_F64, Params, Report, Scalars, Vacuum, check, lib
 
 _DT = {torch.float32: LF_F32, torch.float64: LF_F64}
 
@@ -49,6 +49,35 @@ def autotune(N: int, L: float, dt: float, beta: int, c1: float, G: float, r: flo
                             size.value, cache_path.encode() if cache_path else None, ctypes.byref(best),
                             ctypes.byref(ms)))
     return dict(tile_x=best.tile_x, tile_y=best.tile_y, zchunk=best.zchunk, ms=ms.value)
+
+
+def _vacuum(spec: dict) -> Vacuum:
+    """lf_vacuum from dict(f0=(f1, f2), u0=(u1, u2), m2=(m1^2, m2^2), eps2, seed,
+    cutoff=0)."""
+    v = Vacuum()
+    for i in range(2):
+        v.f0[i], v.u0[i], v.m2[i] = float(spec["f0"][i]), float(spec["u0"][i]), float(spec["m2"][i])
+    v.eps2 = float(spec["eps2"])
+    v.cutoff = float(spec.get("cutoff", 0.0))
+    v.seed = int(spec["seed"])
+    return v
+
+
+def vacuum_fields(N: int, L: float, spec: dict, device="cuda", stream: torch.cuda.Stream | None = None):
+    """Vacuum initial state generated on the device (liblf's lf_vacuum_fields):
+    (f1, f2, u1, u2) as FP64 tensors of shape (N, N, N).  spec: see _vacuum."""
+    device = torch.device(device)
+    p = Params(int(N), LF_F64, float(L), 1.0, 2, 0, 1.0, 0.0, 1.5, 0.0, 0.0, 0, 0, 0, 0)
+    size = ctypes.c_size_t()
+    check(lib().lf_vacuum_workspace_bytes(ctypes.byref(p), ctypes.byref(size)))
+    ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+    out = [torch.empty((N, N, N), dtype=torch.float64, device=device) for _ in range(4)]
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    v = _vacuum(spec)
+    check(lib().lf_vacuum_fields(ctypes.byref(p), ctypes.byref(v), ctypes.c_void_p(st.cuda_stream),
+                                 ctypes.c_void_p(ws.data_ptr()), size.value,
+                                 *(ctypes.c_void_p(t.data_ptr()) for t in out)))
+    return tuple(out)
 
 
 def _aligned(t: torch.Tensor) -> torch.Tensor:
@@ -104,6 +133,19 @@ class Lattice:
         return (self.N, self.N, self.N)
 
     # ------------------------------------------------------------ init
+    def init_vacuum(self, spec: dict, a0: float = 1.0) -> float:
+        """Generate a vacuum state on the device (lf_init_vacuum; spec as for
+        vacuum_fields) and initialise from it with the Friedmann a'_0, which
+        is returned."""
+        size = ctypes.c_size_t()
+        check(lib().lf_init_vacuum_workspace_bytes(ctypes.byref(self.params), ctypes.byref(size)))
+        ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        ad0 = ctypes.c_double()
+        v = _vacuum(spec)
+        check(lib().lf_init_vacuum(self._ctx, ctypes.byref(v), float(a0), ctypes.c_void_p(ws.data_ptr()),
+                                   size.value, ctypes.byref(ad0)))
+        return ad0.value
+
     def init(self, f1, f2, v1, v2, a0: float, ad0: float) -> None:
         """Synchronised program-unit state at tau = 0 (float32 or float64 tensors)."""
         ts = [_aligned(t) for t in (f1, f2, v1, v2)]

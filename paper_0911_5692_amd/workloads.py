@@ -102,6 +102,15 @@ BENCH_SHAPES = {
 }
 
 
+def vacuum_spec(w: Workload, seed: int) -> dict:
+    """Spectrum of the vacuum workloads for the device generator
+    (Lattice.init_vacuum / vacuum_fields): f = (1, 0) + fluctuations,
+    u = (U0_INFLATON, 0) + fluctuations, m_eff^2 = (c1, G) at f1 = 1, f2 = 0,
+    amplitude EPS_VACUUM, cut at N/4."""
+    return dict(f0=(1.0, 0.0), u0=(U0_INFLATON, 0.0), m2=(w.c1, w.G), eps2=EPS_VACUUM ** 2, cutoff=0.0,
+                seed=int(seed))
+
+
 def make_inputs(w: Workload, realization: int = 0) -> dict:
     """Initial fields f1, f2 and rescaled physical velocities u1, u2 (float64),
     a0 = 1.  Seeds: SeedSequence([cfg, realization, field, kind])."""

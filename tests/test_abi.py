@@ -102,3 +102,30 @@ def test_ensemble_workspace_and_validation(LB):
     bad = (LB.Params * 2)(_params(LB, N=16), _params(LB, N=16, dtype=1))
     assert lib.lf_ens_workspace_bytes(2, bad, ctypes.byref(size)) == LB.LF_EINVAL
     assert lib.lf_ens_workspace_bytes(0, arr, ctypes.byref(size)) == LB.LF_EINVAL
+
+
+def _vac(LB, **kw):
+    v = LB.Vacuum()
+    v.f0[0], v.u0[0], v.m2[0], v.m2[1] = 1.0, -0.7, 1.0, 100.0
+    v.eps2, v.cutoff, v.seed = 1e-10, 0.0, 7
+    for k, val in kw.items():
+        if k == "m2":
+            v.m2[1] = val
+        else:
+            setattr(v, k, val)
+    return v
+
+
+@pytest.mark.parametrize("kw,frag", [(dict(eps2=-1.0), "eps2"), (dict(cutoff=-2.0), "cutoff"),
+                                     (dict(m2=-1e6), "imaginary"), (dict(eps2=float("inf")), "eps2")])
+def test_vacuum_spec_rejected_before_any_device_call(LB, kw, frag):
+    lib = LB.lib()
+    p = _params(LB, N=16, dtype=1)
+    buf = ctypes.c_void_p(0x100000)
+    rc = lib.lf_vacuum_fields(ctypes.byref(p), ctypes.byref(_vac(LB, **kw)), None, buf, 1 << 30, buf, buf, buf, buf)
+    assert rc == LB.LF_EINVAL
+    assert frag in lib.lf_last_error().decode()
+    rc = lib.lf_vacuum_fields(ctypes.byref(p), ctypes.byref(_vac(LB)), None, None, 1 << 30, buf, buf, buf, buf)
+    assert rc == LB.LF_EINVAL and "workspace" in lib.lf_last_error().decode()
+    ad0 = ctypes.c_double()
+    assert lib.lf_init_vacuum(None, ctypes.byref(_vac(LB)), 1.0, buf, 1 << 30, ctypes.byref(ad0)) == LB.LF_EINVAL
