@@ -331,6 +331,27 @@ int lf_init_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes);
 int lf_init_vacuum(lf_ctx *ctx, const lf_vacuum *v, double a0, void *workspace, size_t ws_bytes,
                    double *ad0_out);
 
+/* ---- power spectra (the FFT diagnostics named as the next step in Sec. IV)
+ * Shell average of the discrete Fourier power of one synchronised field
+ * g = f1, f2, v1 or v2 (which = 0..3) at time k:
+ *   G_n = sum_x g(x) exp(-2 pi i n.x/N),  shell s = rint(|n|),
+ *   count[s] = number of lattice modes with rint(|n|) = s,
+ *   power[s] = (L^3/N^6) sum_{rint|n| = s} |G_n|^2 / count[s]  (0 if empty),
+ * so that sum_s count[s] power[s] = (L^3/N^3) sum_x g^2, and a field with
+ * power spectrum P(k) (normalised as <g^2> = sum_k P(k)/L^3) has
+ * E power[s] = P on shell s.  FP64; bitwise reproducible. */
+
+/* Shells that hold every mode of an N^3 lattice: rint(sqrt(3) (N div 2)) + 1
+ * (returns the count, 0 for N < 1). */
+int lf_spectrum_bins(int N);
+/* Device scratch for lf_spectrum (one FP64 field, the half spectrum, the FFT
+ * work area and per-plane partial sums).  Needs a device. */
+int lf_spectrum_workspace_bytes(const lf_params *p, size_t *out_bytes);
+/* power, count: HOST arrays of nbins doubles, 1 <= nbins <= lf_spectrum_bins(N)
+ * (shells >= nbins are left out).  Blocking. */
+int lf_spectrum(lf_ctx *ctx, int which, int nbins, double *power, double *count, void *workspace,
+                size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,6 +104,10 @@ SIGNATURES = {
     "lf_init_vacuum_workspace_bytes": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lf_init_vacuum": ([_vp, ctypes.POINTER(Vacuum), ctypes.c_double, _vp, ctypes.c_size_t,
                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "lf_spectrum_bins": ([ctypes.c_int], ctypes.c_int),  # returns the count, not a status
+    "lf_spectrum_workspace_bytes": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lf_spectrum": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                     ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t], ctypes.c_int),
 }
 
 

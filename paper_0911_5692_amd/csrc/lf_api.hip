@@ -833,6 +833,52 @@ int lf_init_vacuum(lf_ctx *c, const lf_vacuum *v, double a0, void *workspace, si
     return lf_init_physical(c, f[0], f[1], f[2], f[3], LF_F64, a0, ad0_out);
 }
 
+int lf_spectrum_bins(int N) { return N >= 1 ? spectrum_bins(N) : 0; }
+
+int lf_spectrum_workspace_bytes(const lf_params *p, size_t *out_bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    char msg[256];
+    size_t b = 0;
+    if (spectrum_workspace_bytes(p->N, &b, msg, sizeof msg)) return fail(LF_EHIP, "%s", msg);
+    *out_bytes = vac_array_bytes(p->N) + b;
+    return LF_OK;
+}
+
+int lf_spectrum(lf_ctx *c, int which, int nbins, double *power, double *count, void *workspace, size_t ws_bytes)
+{
+    if (!c) return fail(LF_EINVAL, "ctx is NULL");
+    if (which < 0 || which > 3) return fail(LF_EINVAL, "which=%d: 0..3 = f1, f2, v1, v2", which);
+    const int nmax = spectrum_bins(c->p.N);
+    if (nbins < 1 || nbins > nmax) return fail(LF_EINVAL, "nbins=%d out of range [1, %d]", nbins, nmax);
+    if (!power || !count) return fail(LF_EINVAL, "power and count must be host arrays");
+    int rc;
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+    if (!c->inited) return fail(LF_ESTATE, "lf_spectrum before lf_init");
+    const size_t arr = vac_array_bytes(c->p.N);
+    if (ws_bytes < arr) return fail(LF_ENOMEM, "workspace of %zu bytes is smaller than one array", ws_bytes);
+    // the synchronised deviation of field `which` and, in the scalar slot,
+    // its homogeneous value (background at time k)
+    double *dev = (double *)workspace;
+    const int fld = which & 1, vel = which >> 1;
+    const double h = 0.5 * c->p.dt;
+    launch_sync_deviation(c->p.dtype, c->buf[c->cur][fld], c->buf[c->cur][2 + fld], dev, c->p.N, h, vel,
+                          c->stream);
+    HIPCHK(hipGetLastError());
+    DevScalars hs;
+    HIPCHK(hipMemcpyAsync(&hs, c->S, sizeof hs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double bg = vel ? hs.bg_v[fld] : hs.bg_f[fld] - h * hs.bg_v[fld];
+    HIPCHK(hipMemcpyAsync(c->tot, &bg, sizeof bg, hipMemcpyHostToDevice, c->stream));
+    char msg[256];
+    const int e = spectrum_compute(c->p.N, c->p.L, dev, c->tot, nbins, c->stream, (char *)workspace + arr,
+                                   ws_bytes - arr, power, count, msg, sizeof msg);
+    if (e) return fail(e == 2 ? LF_ENOMEM : LF_EHIP, "%s", msg);
+    return LF_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- autotuner

@@ -112,6 +112,8 @@ void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4]
 void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],
                        int N, const DevParams *P, const DevScalars *S, int synchronized,
                        hipStream_t st);
+void launch_sync_deviation(int dtype, const void *d, const void *e, double *out, int N, double h, int velocity,
+                           hipStream_t st);
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st);
 void launch_fill_synthetic(int dtype, void *const s4[4], int N, DevScalars *S, hipStream_t st);
 // adjoint (lf_adjoint.hip)
@@ -126,12 +128,19 @@ void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStr
 void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st);
 }  // namespace lf
 
-// vacuum initial state (lf_vacuum.hip); nonzero return = failure, message in msg
+// FFT-based parts (lf_fft.hip): vacuum initial state and power spectra;
+// nonzero return = failure, message in msg
 struct lf_vacuum;
 namespace lf {
 size_t vacuum_spectrum_bytes(int N);
 int vacuum_workspace(int N, size_t *bytes, char *msg, size_t len);
 int vacuum_generate(int N, double L, const struct ::lf_vacuum *v, hipStream_t st, void *ws, size_t ws_bytes,
                     double *const out[4], char *msg, size_t len);
+int spectrum_bins(int N);
+int spectrum_workspace_bytes(int N, size_t *bytes, char *msg, size_t len);
+// power, count: host arrays of nbins; dev: FP64 device array N^3 holding the
+// deviation from the homogeneous value bg (device scalar), which enters shell 0
+int spectrum_compute(int N, double L, double *dev, const double *bg, int nbins, hipStream_t st, void *ws,
+                     size_t ws_bytes, double *power, double *count, char *msg, size_t len);
 
 }  // namespace lf

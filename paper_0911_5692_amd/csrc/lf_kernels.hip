@@ -453,6 +453,17 @@ __global__ void __launch_bounds__(256) k_get_fields(const T *__restrict__ d1, co
     }
 }
 
+// Synchronised deviation from the background of one field, FP64:
+// d(k) = d(k+1/2) - h e(k) (h = dt/2) for a field, e(k) for a velocity.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sync_deviation(const T *__restrict__ d, const T *__restrict__ e,
+                                                        double *out, int64_t N3, double h, int velocity)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = velocity ? (double)e[i] : (double)d[i] - h * (double)e[i];
+}
+
 static int grid_for(int64_t n, int per_block, int cap)
 {
     int64_t g = (n + per_block - 1) / per_block;
@@ -647,6 +658,18 @@ void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4]
     if (stencil == 27) rho_p_s<27>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
     else rho_p_s<7>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
     hipLaunchKernelGGL(k_rho_p_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, out_dev);
+}
+
+void launch_sync_deviation(int dtype, const void *d, const void *e, double *out, int N, double h, int velocity,
+                           hipStream_t st)
+{
+    const int64_t N3 = (int64_t)N * N * N;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_sync_deviation<float>, dim3(grid_for(N3, 256, 65536)), dim3(256), 0, st,
+                           (const float *)d, (const float *)e, out, N3, h, velocity);
+    else
+        hipLaunchKernelGGL(k_sync_deviation<double>, dim3(grid_for(N3, 256, 65536)), dim3(256), 0, st,
+                           (const double *)d, (const double *)e, out, N3, h, velocity);
 }
 
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st)

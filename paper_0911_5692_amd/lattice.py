@@ -146,6 +146,25 @@ class Lattice:
                                    size.value, ctypes.byref(ad0)))
         return ad0.value
 
+    def spectrum(self, which: str = "f1", nbins: int | None = None):
+        """Shell-averaged power spectrum of a synchronised field (lf_spectrum):
+        which in f1, f2, v1, v2.  Returns (power, count) as float64 numpy
+        arrays of nbins (default: every shell)."""
+        import numpy as np
+
+        idx = ("f1", "f2", "v1", "v2").index(which)
+        nmax = lib().lf_spectrum_bins(self.N)
+        nb = nmax if nbins is None else int(nbins)
+        size = ctypes.c_size_t()
+        check(lib().lf_spectrum_workspace_bytes(ctypes.byref(self.params), ctypes.byref(size)))
+        ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        power = np.zeros(nb)
+        count = np.zeros(nb)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().lf_spectrum(self._ctx, idx, nb, power.ctypes.data_as(dp), count.ctypes.data_as(dp),
+                                ctypes.c_void_p(ws.data_ptr()), size.value))
+        return power, count
+
     def init(self, f1, f2, v1, v2, a0: float, ad0: float) -> None:
         """Synchronised program-unit state at tau = 0 (float32 or float64 tensors)."""
         ts = [_aligned(t) for t in (f1, f2, v1, v2)]

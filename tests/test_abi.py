@@ -129,3 +129,11 @@ def test_vacuum_spec_rejected_before_any_device_call(LB, kw, frag):
     assert rc == LB.LF_EINVAL and "workspace" in lib.lf_last_error().decode()
     ad0 = ctypes.c_double()
     assert lib.lf_init_vacuum(None, ctypes.byref(_vac(LB)), 1.0, buf, 1 << 30, ctypes.byref(ad0)) == LB.LF_EINVAL
+
+
+def test_spectrum_arguments_checked_before_any_device_call(LB):
+    lib = LB.lib()
+    assert lib.lf_spectrum_bins(0) == 0 and lib.lf_spectrum_bins(512) == 444
+    buf = (ctypes.c_double * 8)()
+    assert lib.lf_spectrum(None, 0, 4, buf, buf, ctypes.c_void_p(0x100000), 1 << 20) == LB.LF_EINVAL
+    assert "ctx" in lib.lf_last_error().decode()
