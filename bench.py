@@ -64,10 +64,10 @@ def cpu_baseline(w, ic) -> dict:
             "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
 
 
-def time_device_init(w, dtype) -> dict:
-    """Wall time of the on-device vacuum initialisation (noise, FFTs, filter,
-    Friedmann initialisation) at the workload's size: first call (FFT plan
-    setup included) and a second one."""
+def time_extras(w, dtype) -> tuple[dict, dict]:
+    """Wall times at the workload's size of the on-device vacuum
+    initialisation (noise, FFTs, filter, Friedmann initialisation) and of one
+    power spectrum (f1): first call (FFT plan setup included) and a second."""
     import torch
 
     from paper_0911_5692_amd import Lattice
@@ -75,15 +75,21 @@ def time_device_init(w, dtype) -> dict:
 
     spec = W.vacuum_spec(w, seed=w.cfg)
     lat = Lattice(**w.model(), dtype=dtype, device="cuda:0")
-    out = {}
-    for key in ("first_ms", "warm_ms"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lat.init_vacuum(spec, 1.0)
-        torch.cuda.synchronize()
-        out[key] = round((time.perf_counter() - t0) * 1e3, 2)
+
+    def timed(fn):
+        out = {}
+        for key in ("first_ms", "warm_ms"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            out[key] = round((time.perf_counter() - t0) * 1e3, 2)
+        return out
+
+    init = timed(lambda: lat.init_vacuum(spec, 1.0))
+    spectrum = timed(lambda: lat.spectrum("f1"))
     lat.close()
-    return out
+    return init, spectrum
 
 
 def main() -> int:
@@ -96,7 +102,7 @@ def main() -> int:
                     help="eager steps timed per kernel with HIP events (roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-init-timing", action="store_true",
-                    help="skip timing the on-device vacuum initialisation")
+                    help="skip timing the on-device vacuum initialisation and spectrum")
     ap.add_argument("--autotune", action="store_true",
                     help="re-run the launch-shape autotuner instead of the committed shape")
     args = ap.parse_args()
@@ -159,11 +165,11 @@ def main() -> int:
     lat.close()
     torch.cuda.synchronize()
 
-    init = None
+    init = spectrum = None
     if not args.no_init_timing:
-        init = time_device_init(w, dtype)
+        init, spectrum = time_extras(w, dtype)
         init["host_generator_s"] = round(host_inputs_s, 2)
-        log(f"device vacuum initialisation: {init}")
+        log(f"device vacuum initialisation: {init}; spectrum: {spectrum}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -198,6 +204,7 @@ def main() -> int:
                      "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "init": init,
+        "spectrum": spectrum,
     }
     print(json.dumps(line), flush=True)
     return 0
