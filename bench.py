@@ -92,6 +92,38 @@ def time_extras(w, dtype) -> tuple[dict, dict]:
     return init, spectrum
 
 
+PAPER_MS_PER_STEP = 22.0  # Sec. III: 256^3, 2 fields, GTX 260, FP32, 27-point, energy kernel every 512 steps
+
+
+def time_paper_config(blocks: int = 4) -> dict:
+    """The configuration the paper times (Sec. III): 256^3, two fields,
+    V = m^2 phi^2/2 + g^2 phi^2 chi^2/2, dt = 2^-10/m, FP32, 27-point
+    Laplacian, with the energy-density and pressure kernel once every 512
+    steps.  Vacuum initial state generated on the device.  Wall time per step
+    over `blocks` x 512 steps (the rho/p call at each block end included)."""
+    import torch
+
+    from paper_0911_5692_amd import Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    w = W.PAPER_256_S27
+    lat = Lattice(**w.model(), dtype=torch.float32, device="cuda:0", **W.BENCH_SHAPES[w.name])
+    lat.init_vacuum(W.vacuum_spec(w, seed=w.cfg), 1.0)
+    lat.step(512)
+    lat.rho_p(arrays=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        lat.step(512)
+        lat.rho_p(arrays=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / (512 * blocks)
+    lat.close()
+    return {"workload": w.name, "stencil": 27, "N": w.N, "steps": 512 * blocks, "ms_per_step": round(ms, 5),
+            "paper_ms_per_step": PAPER_MS_PER_STEP, "paper_hardware": "GTX 260 (context only)",
+            "speedup": round(PAPER_MS_PER_STEP / ms, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +135,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-init-timing", action="store_true",
                     help="skip timing the on-device vacuum initialisation and spectrum")
+    ap.add_argument("--no-paper-config", action="store_true",
+                    help="skip timing the paper's own 256^3 27-point configuration")
     ap.add_argument("--autotune", action="store_true",
                     help="re-run the launch-shape autotuner instead of the committed shape")
     args = ap.parse_args()
@@ -171,6 +205,11 @@ def main() -> int:
         init["host_generator_s"] = round(host_inputs_s, 2)
         log(f"device vacuum initialisation: {init}; spectrum: {spectrum}")
 
+    paper = None
+    if not args.no_paper_config:
+        paper = time_paper_config()
+        log(f"paper's configuration: {paper}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
@@ -205,6 +244,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "init": init,
         "spectrum": spectrum,
+        "paper_config": paper,
     }
     print(json.dumps(line), flush=True)
     return 0

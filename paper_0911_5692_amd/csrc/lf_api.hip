@@ -43,14 +43,16 @@ struct Shape {
     int tile_x, tile_y, zchunk, rows;  // rows: partial-sum rows the step reduction writes
 };
 
-// Automatic launch shape.  Tiles of 128 x 8 for large lattices, narrower ones
-// below.  The z-chunk is chosen so that the whole grid is resident at once
-// (resident blocks = blocks per CU from the occupancy calculator x CU count):
-// all tiles then march their chunks in lockstep and the halo rows a tile
-// shares with its neighbours are still in L2 when they are needed.  The
-// resident count is only queried on a machine with a GPU; elsewhere (and for
-// the workspace size) 3 blocks on 256 CUs is assumed, which only changes the
-// partial-sum row count.
+// Automatic launch shape.  Tiles of 128 x 8 for large lattices (64 x 8 for
+// the 27-point stencil, whose sweep is limited by its arithmetic and prefers
+// more blocks), narrower ones below.  The z-chunk is chosen so that the whole
+// grid is resident at once (resident blocks = blocks per CU from the
+// occupancy calculator x CU count): all tiles then march their chunks in
+// lockstep and the halo rows a tile shares with its neighbours are still in
+// L2 when they are needed.  It is capped at 64 planes, which the autotuner
+// prefers on gfx950 for the large lattices.  The resident count is only
+// queried on a machine with a GPU; elsewhere (and for the workspace size) 3
+// blocks on 256 CUs is assumed, which only changes the partial-sum row count.
 // 7 or 27 (lf_params.stencil 0 means 7).
 int stencil_of(const lf_params *p) { return p->stencil == 27 ? 27 : 7; }
 
@@ -74,8 +76,7 @@ Shape shape_of(const lf_params *p)
         sh.tile_y = p->tile_y;
         sh.tile_x = p->tile_x ? p->tile_x : 64;
     } else if (N >= 256) {
-        // the 27-point FP64 sweep holds 3 blocks per CU only with 64-wide tiles
-        sh.tile_x = (stencil_of(p) == 27 && p->dtype == LF_F64) ? 64 : 128;
+        sh.tile_x = stencil_of(p) == 27 ? 64 : 128;
         sh.tile_y = 8;
     } else {
         sh.tile_x = 64;
@@ -94,7 +95,7 @@ Shape shape_of(const lf_params *p)
         int nzc = resident_blocks(p, sh.tile_x, sh.tile_y) / per_slab;
         nzc = nzc < 1 ? 1 : nzc;
         int dz = (N + nzc - 1) / nzc;
-        dz = dz < 8 ? 8 : dz;
+        dz = dz < 8 ? 8 : (dz > 64 ? 64 : dz);
         sh.zchunk = dz < N ? dz : N;
     }
     sh.rows = sweep_lds_blocks(N, sh.tile_x, sh.tile_y, sh.zchunk);

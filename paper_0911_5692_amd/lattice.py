@@ -221,6 +221,32 @@ class Lattice:
         check(lib().lf_rho_p(self._ctx, ptrs[0], ptrs[1], _DT[dtype], avg))
         return out[0], out[1], dict(rho=avg[0], p=avg[1], w=avg[2])
 
+    def history(self, steps: int, every: int, w: bool = True) -> dict:
+        """Evolve `steps` steps and record, at the start and after every
+        `every` steps, the synchronised step, a, a'/a, rho, the Friedmann
+        residual R and (w=True) the equation of state w = <p>/<rho>: the
+        series the paper plots in Sec. III.  Returns numpy arrays."""
+        import numpy as np
+
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        rec = {k: [] for k in ("step", "a", "hubble", "rho", "R", "w")}
+
+        def take():
+            e = self.energies()
+            for k in ("step", "a", "hubble", "rho", "R"):
+                rec[k].append(e[k])
+            rec["w"].append(self.rho_p(arrays=False)[2]["w"] if w else float("nan"))
+
+        take()
+        done = 0
+        while done < steps:
+            n = min(every, steps - done)
+            self.step(n)
+            done += n
+            take()
+        return {k: np.asarray(v) for k, v in rec.items()}
+
     def fields(self, synchronized: bool = False, dtype: torch.dtype = torch.float64):
         """(f1, f2, v1, v2) as new tensors: f(k+1/2) and v(k), or f(k), v(k)."""
         out = [torch.empty(self.shape, dtype=dtype, device=self.device) for _ in range(4)]

@@ -82,6 +82,9 @@ CFG3 = Workload("m2phi2_512c_f32", 3, 512, 10.0, 2.0 ** -10, 2, 1.0, 2.5e5, 1.5,
 CFG5 = _lphi4("lphi4_128c_f32_adjoint", 5, 128, 500, "f32", "white")
 # the 512^3 m^2 phi^2 run with the paper's own 27-point Laplacian (same inputs)
 CFG3_S27 = replace(CFG3, name="m2phi2_512c_f32_s27", stencil=27)
+# the configuration the paper times (Sec. III): 256^3, the same model and dt,
+# FP32, 27-point Laplacian (box side at the benchmark's dx)
+PAPER_256_S27 = replace(CFG3_S27.resized(256), name="m2phi2_256c_f32_s27")
 # ensemble: 48 x 64^3 + 16 x 96^3 + 4 x 160^3 of the lambda phi^4 model, own dx and dt each
 ENSEMBLE_SIZES = [64] * 48 + [96] * 16 + [160] * 4
 ENSEMBLE_STEPS = 500
@@ -92,13 +95,14 @@ def ensemble_members():
             for r, n in enumerate(ENSEMBLE_SIZES)]
 
 
-WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5, CFG3_S27)}
+WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5, CFG3_S27, PAPER_256_S27)}
 
 # Sweep launch shapes used by the benchmark, as chosen by lf_autotune on an
 # MI355X (gfx950); re-run the autotuner (bench.py --autotune) on other parts.
 BENCH_SHAPES = {
     CFG3.name: dict(tile_x=128, tile_y=8, zchunk=64),
     CFG3_S27.name: dict(tile_x=64, tile_y=8, zchunk=64),
+    PAPER_256_S27.name: dict(tile_x=64, tile_y=8, zchunk=43),
 }
 
 

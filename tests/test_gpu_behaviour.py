@@ -187,3 +187,28 @@ def test_rho_p_matches_oracle(dtype, tol):
         assert abs(gavg[k] - avg[k]) <= tol * abs(avg[k]), k
     _, _, only = lat.rho_p(arrays=False)
     assert only == gavg
+
+
+@pytest.mark.parametrize("stencil", [7, 27])
+def test_history_series_matches_oracle(stencil):
+    """a(t), H, rho, R and w(t) recorded every 40 steps (the series the paper
+    plots) against the oracle's at the same steps, FP64."""
+    from dataclasses import replace
+    w = replace(W.CFG3, stencil=stencil).resized(24)
+    ic = W.make_inputs(w)
+    m = O.Model(**w.model())
+    st = O.start_physical(m, ic["f1"], ic["f2"], ic["u1"], ic["u2"], 1.0)
+    lat = make_lattice(w, dtype="f64")
+    lat.init_physical(to_dev(ic["f1"]), to_dev(ic["f2"]), to_dev(ic["u1"]), to_dev(ic["u2"]), 1.0)
+    h = lat.history(200, 40)
+    assert list(h["step"]) == [0, 40, 80, 120, 160, 200]
+    for j in range(len(h["step"])):
+        if j:
+            O.evolve(st, 40)
+        e = O.energies(st)
+        _, _, avg = O.rho_p(st, arrays=False)
+        assert abs(h["a"][j] - e["a"]) <= 1e-12 * e["a"]
+        assert abs(h["hubble"][j] - e["ad"] / e["a"]) <= 1e-11 * abs(e["ad"] / e["a"])
+        assert abs(h["rho"][j] - e["rho"]) <= 1e-10 * e["rho"]
+        assert abs(h["R"][j] - e["R"]) <= 1e-12
+        assert abs(h["w"][j] - avg["w"]) <= 1e-10 * max(1.0, abs(avg["w"]))
