@@ -66,20 +66,3 @@ def gaussian_random_field(N: int, L: float, m_eff2: float, rng: np.random.Genera
     if std is not None:
         f *= std / f.std()
     return f
-
-
-def shell_power(f: np.ndarray, L: float):
-    """Shell-averaged |FFT|^2 * L^3 / N^6 per integer |n| shell (for tests)."""
-    N = f.shape[0]
-    F = sfft.rfftn(f, workers=_WORKERS)
-    nn = _mode_norm(N)
-    wgt = np.ones_like(nn)
-    wgt[..., 1:] = 2.0
-    if N % 2 == 0:
-        wgt[..., -1] = 1.0
-    shell = np.rint(nn).astype(np.int64).ravel()
-    pw = (np.abs(F) ** 2).ravel() * wgt.ravel() * L ** 3 / N ** 6
-    cnt = np.bincount(shell, weights=wgt.ravel())
-    tot = np.bincount(shell, weights=pw)
-    with np.errstate(invalid="ignore", divide="ignore"):
-        return np.arange(len(cnt)), tot / cnt, cnt
