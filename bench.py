@@ -92,6 +92,68 @@ def time_extras(w, dtype) -> tuple[dict, dict]:
     return init, spectrum
 
 
+def time_additions() -> dict:
+    """Measured numbers of the rows and additions beyond the step itself:
+    rho/p per site at 512^3 (algorithmic 16 B read + 8 B written per site,
+    FP32 outputs), the ensemble of uneven lattices (500 steps), and the
+    adjoint of the 128^3 workload (500 steps, checkpoints every 50)."""
+    import torch
+
+    from paper_0911_5692_amd import Ensemble, Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    out = {}
+    w = W.CFG3
+    lat = Lattice(**w.model(), dtype=torch.float32, device="cuda:0", **W.BENCH_SHAPES[w.name])
+    lat.init_vacuum(W.vacuum_spec(w, seed=w.cfg), 1.0)
+    lat.step(20)
+    lat.rho_p(dtype=torch.float32)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lat.rho_p(dtype=torch.float32)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    alg = 24 * w.sites
+    out["rho_p"] = {"N": w.N, "ms": round(ms, 3), "algorithmic_bytes": alg, "GBps": round(alg / ms / 1e6, 1),
+                    "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    lat.close()
+
+    members = W.ensemble_members()
+    ens = Ensemble([m.model() for m in members], dtype=torch.float32, device="cuda:0")
+    for r, m in enumerate(members):
+        ic = W.make_inputs(m, realization=r)
+        ens.init_physical(r, *(torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")),
+                          ic["a0"])
+    ens.step(10)
+    torch.cuda.synchronize()
+    ens.step(W.ENSEMBLE_STEPS)
+    ms = ens.last_step_ms() / W.ENSEMBLE_STEPS
+    sites = sum(m.sites for m in members)
+    out["ensemble"] = {"realizations": len(members), "sites": sites, "ms_per_step": round(ms, 4),
+                       "Gsite_updates_per_s": round(sites / ms / 1e6, 2),
+                       "hbm_frac_algorithmic": round(32 * sites / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    ens.close()
+
+    w5 = W.CFG5
+    ic = W.make_inputs(w5)
+    lat = Lattice(**w5.model(), dtype=torch.float32, device="cuda:0")
+    lat.init_physical(*(torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.adjoint_forward(w5.steps, 50)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.adjoint_backward(1.0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["adjoint"] = {"N": w5.N, "steps": w5.steps, "K": 50, "forward_ms": round((t1 - t0) * 1e3, 1),
+                      "backward_ms": round((t2 - t1) * 1e3, 1)}
+    lat.close()
+    return out
+
+
 PAPER_MS_PER_STEP = 22.0  # Sec. III: 256^3, 2 fields, GTX 260, FP32, 27-point, energy kernel every 512 steps
 
 
@@ -137,6 +199,8 @@ def main() -> int:
                     help="skip timing the on-device vacuum initialisation and spectrum")
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip timing the paper's own 256^3 27-point configuration")
+    ap.add_argument("--no-additions", action="store_true",
+                    help="skip timing rho/p, the ensemble and the adjoint")
     ap.add_argument("--autotune", action="store_true",
                     help="re-run the launch-shape autotuner instead of the committed shape")
     args = ap.parse_args()
@@ -210,6 +274,11 @@ def main() -> int:
         paper = time_paper_config()
         log(f"paper's configuration: {paper}")
 
+    additions = None
+    if not args.no_additions:
+        additions = time_additions()
+        log(f"additions: {additions}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
@@ -245,6 +314,7 @@ def main() -> int:
         "init": init,
         "spectrum": spectrum,
         "paper_config": paper,
+        "additions": additions,
     }
     print(json.dumps(line), flush=True)
     return 0
