@@ -234,9 +234,31 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         __syncthreads();
     }
 
+    // The new values of plane z are stored at the top of iteration z+1, just
+    // before its loads.  The memory counter retires in issue order, so a wait
+    // for those loads then finds stores that have had a whole iteration to
+    // drain.  Stores stream once: non-temporal, so L2 keeps the halo rows.
+    T pe1[KI], pe2[KI], pd1[KI], pd2[KI];
+    bool pend = false;
+    int pz_st = 0;
+    auto flush = [&]() {
+        if (pend) {
+            T *o_e1 = const_cast<T *>(plane(e1n, pz_st)), *o_e2 = const_cast<T *>(plane(e2n, pz_st));
+            T *o_d1 = const_cast<T *>(plane(d1n, pz_st)), *o_d2 = const_cast<T *>(plane(d2n, pz_st));
+#pragma unroll
+            for (int k = 0; k < KI; ++k)
+                if (act[k]) {
+                    __builtin_nontemporal_store(pe1[k], o_e1 + goff[k]);
+                    __builtin_nontemporal_store(pe2[k], o_e2 + goff[k]);
+                    __builtin_nontemporal_store(pd1[k], o_d1 + goff[k]);
+                    __builtin_nontemporal_store(pd2[k], o_d2 + goff[k]);
+                }
+        }
+    };
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     int cur = 0;
     for (int z = z0 - 1; z < z1; ++z, cur ^= 1) {
+        flush();
         // newest prefetch slot: d(z+1+PF), e(z+PF), halo(z+1+PF)
         fill(PF - 1, z + 1 + PF);
 
@@ -244,8 +266,6 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         const bool more = (z + 1 < z1);
         const T *s0 = sd[cur][0], *s1 = sd[cur][1];
         T *n0 = sn[cur][0], *n1 = sn[cur][1];
-        T *o_e1 = const_cast<T *>(plane(e1n, z)), *o_e2 = const_cast<T *>(plane(e2n, z));
-        T *o_d1 = const_cast<T *>(plane(d1n, z)), *o_d2 = const_cast<T *>(plane(d2n, z));
         T zd1[KI], zd2[KI];
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
@@ -256,13 +276,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
             c.force(qc1[k], qc2[k], sa, sb, ia, ib);
             const T ea = ev1[k] + ia, eb = ev2[k] + ib;
             const T na = qc1[k] + c.dt * ea, nb = qc2[k] + c.dt * eb;
-            if (live && act[k]) {
-                // streamed once: non-temporal, so L2 keeps the halo rows instead
-                __builtin_nontemporal_store(ea, o_e1 + goff[k]);
-                __builtin_nontemporal_store(eb, o_e2 + goff[k]);
-                __builtin_nontemporal_store(na, o_d1 + goff[k]);
-                __builtin_nontemporal_store(nb, o_d2 + goff[k]);
-            }
+            pe1[k] = ea; pe2[k] = eb; pd1[k] = na; pd2[k] = nb;
             n0[lsn[k]] = na;
             n1[lsn[k]] = nb;
             zd1[k] = na - dn1[k];
@@ -308,6 +322,8 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
             }
         }
 
+        pend = live;
+        pz_st = z;
         // rotate the queues and the prefetch slots
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
@@ -334,6 +350,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         }
     }
 
+    flush();
     // block partial sums, fixed order
     double v[4] = {acc0, acc1, acc2, acc3};
     __shared__ double red[4][4];

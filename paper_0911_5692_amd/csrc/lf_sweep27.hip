@@ -218,28 +218,54 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     int cur = 0;
     int nb_cur = 0, nb_prev = 2;  // new-value planes of z and z-1
+    // The new values of plane z are stored at the top of iteration z+1, just
+    // before its loads.  The memory counter retires in issue order, so the
+    // wait for those loads at the end of the iteration then finds stores that
+    // have had a whole iteration to drain, not ones issued a moment before.
+    // Stores stream once: non-temporal, so L2 keeps the halo rows instead.
+    T pe1[KI], pe2[KI], pd1[KI], pd2[KI];
+    bool pend = false;
+    int pz_st = 0;
+    auto flush = [&]() {
+        if (pend) {
+            T *o_e1 = const_cast<T *>(plane(e1n, pz_st)), *o_e2 = const_cast<T *>(plane(e2n, pz_st));
+            T *o_d1 = const_cast<T *>(plane(d1n, pz_st)), *o_d2 = const_cast<T *>(plane(d2n, pz_st));
+#pragma unroll
+            for (int k = 0; k < KI; ++k)
+                if (act[k]) {
+                    st_nt(pe1[k], o_e1, goff[k]);
+                    st_nt(pe2[k], o_e2, goff[k]);
+                    st_nt(pd1[k], o_d1, goff[k]);
+                    st_nt(pd2[k], o_d2, goff[k]);
+                }
+        }
+    };
     for (int z = zs; z < z1; ++z) {
+        flush();
         // loads for the next iteration: d(z+3), halo(z+3), e(z+1)
         {
-            const int pz = z + 3;
-            const bool need_d = pz <= z1, need_e = (z + 1 >= z0 - 1) && (z + 1 <= z1 - 1);
+            // unconditional loads (no branch to delay their issue): the plane
+            // index is clamped into the chunk's range, and values of planes the
+            // chunk does not need are never used
+            const int pz = min(z + 3, z1);
+            const int pe = min(max(z + 1, z0 - 1), z1 - 1);
             const T *a1 = plane(d1, pz), *a2 = plane(d2, pz);
-            const T *b1 = plane(e1, z + 1), *b2 = plane(e2, z + 1);
+            const T *b1 = plane(e1, pe), *b2 = plane(e2, pe);
 #pragma unroll
             for (int k = 0; k < KI; ++k) {
-                ld1[k] = need_d ? ld_at(a1, goff[k]) : T(0);
-                ld2[k] = need_d ? ld_at(a2, goff[k]) : T(0);
-                le1[k] = need_e ? ld_at(b1, goff[k]) : T(0);
-                le2[k] = need_e ? ld_at(b2, goff[k]) : T(0);
+                ld1[k] = ld_at(a1, goff[k]);
+                ld2[k] = ld_at(a2, goff[k]);
+                le1[k] = ld_at(b1, goff[k]);
+                le2[k] = ld_at(b2, goff[k]);
             }
-            rld1 = (hasr && need_d) ? ld_at(a1, roff) : T(0);
-            rld2 = (hasr && need_d) ? ld_at(a2, roff) : T(0);
-            rle1 = (hasr && need_e) ? ld_at(b1, roff) : T(0);
-            rle2 = (hasr && need_e) ? ld_at(b2, roff) : T(0);
+            rld1 = ld_at(a1, roff);
+            rld2 = ld_at(a2, roff);
+            rle1 = ld_at(b1, roff);
+            rle2 = ld_at(b2, roff);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                lh1[m] = (hash[m] && need_d) ? ld_at(a1, hoff[m]) : T(0);
-                lh2[m] = (hash[m] && need_d) ? ld_at(a2, hoff[m]) : T(0);
+                lh1[m] = ld_at(a1, hoff[m]);
+                lh2[m] = ld_at(a2, hoff[m]);
             }
         }
 
@@ -264,15 +290,7 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             const T ea = ev1[k] + ia, eb = ev2[k] + ib;
             na1[k] = qc1[k] + c.dt * ea;
             na2[k] = qc2[k] + c.dt * eb;
-            if (live && act[k]) {
-                T *o_e1 = const_cast<T *>(plane(e1n, z)), *o_e2 = const_cast<T *>(plane(e2n, z));
-                T *o_d1 = const_cast<T *>(plane(d1n, z)), *o_d2 = const_cast<T *>(plane(d2n, z));
-                // streamed once: non-temporal, so L2 keeps the halo rows instead
-                st_nt(ea, o_e1, goff[k]);
-                st_nt(eb, o_e2, goff[k]);
-                st_nt(na1[k], o_d1, goff[k]);
-                st_nt(na2[k], o_d2, goff[k]);
-            }
+            pe1[k] = ea; pe2[k] = eb; pd1[k] = na1[k]; pd2[k] = na2[k];
             // planes below z0-1 are written too: their slots are rewritten
             // before the first read
             n0[lsn[k]] = na1[k];
@@ -297,7 +315,8 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             n1[rlsn] = rna2;
         }
         // stage plane z+2 into the other buffer (loaded one iteration ago;
-        // past z1 the registers hold zeros and the buffer is not read again)
+        // past z1 the registers repeat a clamped plane and the buffer is not
+        // read again)
         {
             T *t0 = sd[cur ^ 1][0], *t1 = sd[cur ^ 1][1];
 #pragma unroll
@@ -365,11 +384,14 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         rev1 = rle1; rev2 = rle2;
 #pragma unroll
         for (int m = 0; m < 2; ++m) { hv1[m] = lh1[m]; hv2[m] = lh2[m]; }
+        pend = live;
+        pz_st = z;
         cur ^= 1;
         nb_prev = nb_cur;
         nb_cur = nb_cur == 2 ? 0 : nb_cur + 1;
     }
 
+    flush();
     // block partial sums, fixed order
     double v[4] = {acc0, acc1, acc2, acc3};
     __shared__ double red[4][4];

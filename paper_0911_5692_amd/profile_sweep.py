@@ -116,6 +116,16 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
         stats = _rows(_find(trace_dir, "kernel_stats.csv"))
         res["kernel_stats"] = [dict(name=r["Name"][:90], calls=int(r["Calls"]), avg_ns=float(r["AverageNs"]),
                                     pct=float(r["Percentage"])) for r in stats[:8]]
+        # sweep launches per (kernel, grid): the statistics above merge every
+        # lattice size the traced run launched one kernel on
+        groups: dict = {}
+        for r in _rows(_find(trace_dir, "kernel_trace.csv")):
+            if is_sweep(r["Kernel_Name"]):
+                key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
+                groups.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        res["sweep_launches"] = sorted(
+            (dict(name=k[0], blocks=k[1], calls=len(v), avg_ns=sum(v) / len(v)) for k, v in groups.items()),
+            key=lambda g: -g["calls"] * g["avg_ns"])
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, f"sweep_traffic_{workload}.json"), "w") as fh:
         json.dump(res, fh, indent=1)
@@ -138,6 +148,10 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
             fh.write("\nKernel trace (rocprofv3 --kernel-trace --stats):\n\n| kernel | calls | avg ns | % |\n|---|---|---|---|\n")
             for k in res["kernel_stats"]:
                 fh.write(f"| {k['name']} | {k['calls']} | {k['avg_ns']:.0f} | {k['pct']:.1f} |\n")
+            fh.write("\nSweep launches of the same trace by grid (kernel trace, end - start):\n\n"
+                     "| kernel | blocks | calls | avg ns |\n|---|---|---|---|\n")
+            for g in res["sweep_launches"]:
+                fh.write(f"| {g['name']} | {g['blocks']} | {g['calls']} | {g['avg_ns']:.0f} |\n")
     return res
 
 
