@@ -257,8 +257,8 @@ int lf_adj_backward(lf_ctx *ctx, double dL, double *dL_dG, void *g_f1, void *g_f
  * with its own a(t), background and averages) and one persistent sweep whose
  * grid walks a static list of (realization, tile, z-chunk) work items.  The
  * sweep tile is per_real[0].tile_x/tile_y (default 64 x 8) for all
- * realizations; z-chunks may differ per realization (default 16 planes, 32
- * above N = 128).  Each realization's state matches a single-lattice run
+ * realizations; z-chunks may differ per realization (default N/2 planes,
+ * at least 8, or N when N < 8).  Each realization's state matches a single-lattice run
  * with the same parameters to rounding. */
 int lf_ens_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
 int lf_ens_create(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,
@@ -313,13 +313,15 @@ typedef struct lf_vacuum {
 
 /* Scratch for lf_vacuum_fields: the half spectrum of one array
  * (N^2 (N/2+1) complex doubles) plus the FFT work area.  Needs a device (the
- * FFT plans are created to size their work area). */
+ * FFT plans are made to size their work area).  The hipFFT plans of each
+ * (device, N) are made once per process and kept; they hold small tables of
+ * their own but no work area. */
 int lf_vacuum_workspace_bytes(const lf_params *p, size_t *out_bytes);
 /* Generate f1, f2, u1, u2 (FP64 device arrays of N^3, 256-byte aligned,
  * caller-owned) for the lattice of p on `stream`.  The large buffers come
- * from `workspace`; hipFFT's plans keep small tables of their own for the
- * duration of the call.  Blocking; same seed, N and spectrum give bitwise
- * the same arrays. */
+ * from `workspace`.  Blocking; same seed, N and spectrum give bitwise the
+ * same arrays.  Calls from several threads are safe (the shared plans are
+ * bound to a stream and work area under a lock). */
 int lf_vacuum_fields(const lf_params *p, const lf_vacuum *v, void *stream, void *workspace,
                      size_t ws_bytes, double *f1, double *f2, double *u1, double *u2);
 /* Scratch for lf_init_vacuum: four FP64 arrays of N^3 plus
