@@ -11,7 +11,7 @@ namespace lf {
 constexpr int kMaxBeta = 6;
 constexpr int kNPart = 4;   // step reduction: sum|d+ f1|^2, sum|d+ f2|^2, sum f1^beta, sum f1^2 f2^2
 constexpr int kNMom = 10;   // input moments (see k_input_moments)
-constexpr int kNEn = 6;     // energy sums (see k_energy_part)
+constexpr int kNEn = 6;     // energy sums (see k_diag_march)
 constexpr int kStage2Threads = 256;
 
 // Model parameters in device memory (read by the scale-factor kernel, so a

@@ -297,49 +297,164 @@ __global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *
 
 // ---------------------------------------------------------------- energies
 
-// Per-block sums at the synchronised time (FP64 per site):
+// Both diagnostics below need, per site at the synchronised time k, the
+// synchronised deviations s_i = d_i(k+1/2) - (dt/2) e_i(k) at the site and at
+// its forward neighbours (+x, +y, +z for the 7-point gradient; the 13 forward
+// bonds of the 27-point Dirichlet form, which reach x-1..x+1, y-1..y+1 and
+// z..z+1), and the velocity deviation e_i(k) at the site.
+//
+// k_diag_march: a block owns a 64 x 4 column tile and marches z over a chunk.
+// The s values of planes z and z+1 sit in LDS with a one-cell ring (three
+// buffers, one barrier per plane); plane z+2 is loaded into registers while
+// plane z is evaluated.  Each array element is read from HBM about once,
+// plus the ring (mostly L2 hits) and one plane per chunk, instead of once per
+// neighbour.  The grid walks a static list of (tile, chunk) items, so any N
+// fits a fixed number of partial rows; per-site arithmetic is FP64 and the
+// block sums are deterministic.
+constexpr int kDiagX = 64, kDiagY = 4;
+constexpr int kDiagLW = kDiagX + 2, kDiagLH = kDiagY + 2;  // LDS plane with its ring
+
+// ring cells a plane needs beyond the tile: 7 points, the +x column and the
+// +y row; 27 points, the whole ring
+template <int ST>
+constexpr int diag_ring() { return ST == 27 ? 2 * kDiagLW + 2 * kDiagY : kDiagX + kDiagY; }
+
+template <int ST>
+__device__ inline void diag_ring_cell(int c, int &lx, int &ly)
+{
+    if (ST == 27) {
+        if (c < kDiagLW) { lx = c - 1; ly = -1; }
+        else if (c < 2 * kDiagLW) { lx = c - kDiagLW - 1; ly = kDiagY; }
+        else if (c < 2 * kDiagLW + kDiagY) { lx = -1; ly = c - 2 * kDiagLW; }
+        else { lx = kDiagX; ly = c - 2 * kDiagLW - kDiagY; }
+    } else {
+        if (c < kDiagY) { lx = kDiagX; ly = c; }
+        else { lx = c - kDiagY; ly = kDiagY; }
+    }
+}
+
+// MODE 0: the energy sums of k_energy_final (kNEn per block row):
 //  0,1: sum (v_i - r (a'/a) f_i)^2   2,3: raw gradient sums of f_i
 //  4: sum f1^beta   5: sum f1^2 f2^2
-template <typename T, int ST>
-__global__ void __launch_bounds__(256) k_energy_part(const T *__restrict__ d1, const T *__restrict__ d2,
-                                                     const T *__restrict__ e1, const T *__restrict__ e2,
-                                                     int N, const DevParams *__restrict__ P,
-                                                     const DevScalars *__restrict__ S, double *part)
+// MODE 1: energy density and pressure per site (eq. rho-pres in program
+// units): rho = sum_i K_i + G_i + V_pr, p = sum_i K_i - G_i/3 - V_pr,
+// K_i = (v_i - r (a'/a) f_i)^2/2, G_i = a^(-2s-2) grad2(f_i)/2 with grad2 the
+// stencil's gradient energy density; rho, p may be NULL.  Sums: rho, p.
+template <typename T, int ST, int MODE, typename To>
+__global__ void __launch_bounds__(256) k_diag_march(const T *__restrict__ d1, const T *__restrict__ d2,
+                                                    const T *__restrict__ e1, const T *__restrict__ e2, int N,
+                                                    int zchunk, int ntx, int nty, int nitems,
+                                                    const DevParams *__restrict__ P,
+                                                    const DevScalars *__restrict__ S, To *__restrict__ rho,
+                                                    To *__restrict__ pr, double *__restrict__ part)
 {
-    const int64_t N3 = (int64_t)N * N * N;
-    const double h = 0.5 * P->dt, r = P->r;
+    constexpr int NV = MODE == 0 ? kNEn : 2;
+    constexpr int NR = diag_ring<ST>();
+    constexpr int PL = kDiagLW * kDiagLH;
+    __shared__ double sv[3][2][PL];  // [buffer][field][plane with ring]
+
+    const double h = 0.5 * P->dt, r = P->r, sx = P->s;
     const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
     const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
     const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
+    const double gfac = 0.5 * pow(ak, -2.0 * sx - 2.0) * P->gw / (P->dx * P->dx);
+    const double cv1 = P->c1 * pow(ak, P->p1) / (double)P->beta, cv2 = 0.5 * P->G * pow(ak, P->p2);
     const int beta = P->beta;
-    double acc[kNEn];
+    const int64_t NN = (int64_t)N * N;
+
+    const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+    const int slot = (ly + 1) * kDiagLW + lx + 1;
+    const bool hasr = t < NR;
+    int rx = 0, ry = 0;
+    if (hasr) diag_ring_cell<ST>(t, rx, ry);
+    const int rslot = (ry + 1) * kDiagLW + rx + 1;
+    auto wrap = [N](int v) { return ((v % N) + N) % N; };
+    auto plane = [&](const T *a, int z) { return a + (int64_t)(z >= N ? z - N : z) * NN; };
+
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < kNEn; ++i) acc[i] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const Wrap w(i, N);
-        // synchronised deviations d(k) = d(k+1/2) - dt/2 e(k)
-        auto sy1 = [&](int dx, int dy, int dz) {
-            const int64_t j = w(dx, dy, dz);
-            return (double)d1[j] - h * (double)e1[j];
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tx = item % ntx, rest = item / ntx, ty = rest % nty, tz = rest / nty;
+        const int x0 = tx * kDiagX, y0 = ty * kDiagY, z0 = tz * zchunk;
+        const int z1 = min(z0 + zchunk, N);
+        const bool act = (x0 + lx < N) && (y0 + ly < N);
+        // in-plane offsets, wrapped (inactive lanes hold the periodic images
+        // their active neighbours need)
+        const int off = wrap(y0 + ly) * N + wrap(x0 + lx);
+        const int roff = wrap(y0 + ry) * N + wrap(x0 + rx);
+
+        // registers of the plane in flight: site and ring cell, 4 arrays
+        T rd1, rd2, re1, re2, hd1 = 0, hd2 = 0, he1 = 0, he2 = 0;
+        auto load = [&](int z) {
+            const T *a1 = plane(d1, z), *a2 = plane(d2, z), *b1 = plane(e1, z), *b2 = plane(e2, z);
+            rd1 = a1[off]; rd2 = a2[off]; re1 = b1[off]; re2 = b2[off];
+            if (hasr) { hd1 = a1[roff]; hd2 = a2[roff]; he1 = b1[roff]; he2 = b2[roff]; }
         };
-        auto sy2 = [&](int dx, int dy, int dz) {
-            const int64_t j = w(dx, dy, dz);
-            return (double)d2[j] - h * (double)e2[j];
+        auto stage = [&](int b) {
+            sv[b][0][slot] = (double)rd1 - h * (double)re1;
+            sv[b][1][slot] = (double)rd2 - h * (double)re2;
+            if (hasr) {
+                sv[b][0][rslot] = (double)hd1 - h * (double)he1;
+                sv[b][1][rslot] = (double)hd2 - h * (double)he2;
+            }
         };
-        const double s1 = (double)d1[i] - h * (double)e1[i];
-        const double s2 = (double)d2[i] - h * (double)e2[i];
-        const double x1 = gs1 + s1, x2 = gs2 + s2;
-        const double q1 = (vb1 + (double)e1[i]) - r * hub * x1;
-        const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
-        acc[0] += q1 * q1;
-        acc[1] += q2 * q2;
-        acc[2] += grad_raw<ST>(sy1, s1);
-        acc[3] += grad_raw<ST>(sy2, s2);
-        acc[4] += ipow_d(x1, beta);
-        acc[5] += x1 * x1 * x2 * x2;
+        // own velocity deviations of planes z and z+1
+        double ec1, ec2, en1, en2;
+        load(z0);
+        stage(0);
+        ec1 = (double)re1; ec2 = (double)re2;
+        load(z0 + 1);
+        stage(1);
+        en1 = (double)re1; en2 = (double)re2;
+        if (z0 + 1 < z1) load(z0 + 2);
+        __syncthreads();
+
+        int b0 = 0;
+        for (int z = z0; z < z1; ++z) {
+            const int b1 = b0 == 2 ? 0 : b0 + 1, b2 = b1 == 2 ? 0 : b1 + 1;
+            if (act) {
+                const double *p1 = sv[b0][0], *q1 = sv[b1][0], *p2 = sv[b0][1], *q2 = sv[b1][1];
+                auto sy1 = [&](int dx, int dy, int dz) { return (dz ? q1 : p1)[slot + dy * kDiagLW + dx]; };
+                auto sy2 = [&](int dx, int dy, int dz) { return (dz ? q2 : p2)[slot + dy * kDiagLW + dx]; };
+                const double s1 = p1[slot], s2 = p2[slot];
+                const double x1 = gs1 + s1, x2 = gs2 + s2;
+                const double u1 = (vb1 + ec1) - r * hub * x1;
+                const double u2 = (vb2 + ec2) - r * hub * x2;
+                if (MODE == 0) {
+                    acc[0] += u1 * u1;
+                    acc[1] += u2 * u2;
+                    acc[2] += grad_raw<ST>(sy1, s1);
+                    acc[3] += grad_raw<ST>(sy2, s2);
+                    acc[4] += ipow_d(x1, beta);
+                    acc[5] += x1 * x1 * x2 * x2;
+                } else {
+                    double g = grad_raw<ST>(sy1, s1);
+                    g += grad_raw<ST>(sy2, s2);
+                    const double K = 0.5 * (u1 * u1 + u2 * u2), Gs = gfac * g;
+                    const double V = cv1 * ipow_d(x1, beta) + cv2 * x1 * x1 * x2 * x2;
+                    const double rr = K + Gs + V, pp = K - Gs / 3.0 - V;
+                    const int64_t i = (int64_t)z * NN + off;
+                    // streamed once: non-temporal
+                    if (rho) __builtin_nontemporal_store((To)rr, rho + i);
+                    if (pr) __builtin_nontemporal_store((To)pp, pr + i);
+                    acc[0] += rr;
+                    acc[1] += pp;
+                }
+            }
+            if (z + 1 < z1) {
+                // plane z+2 into the buffer last read for plane z-1
+                stage(b2);
+                ec1 = en1; ec2 = en2;
+                en1 = (double)re1; en2 = (double)re2;
+                if (z + 2 < z1) load(z + 3);
+            }
+            __syncthreads();
+            b0 = b1;
+        }
     }
-    block_sum_store<kNEn>(acc, part + (size_t)blockIdx.x * kNEn);
+    block_sum_store<NV>(acc, part + (size_t)blockIdx.x * NV);
 }
 
 // out: step, a, a', a'/a, K1, K2, G1, G2, P, rho, R, status (as double)
@@ -368,56 +483,6 @@ __global__ void __launch_bounds__(kStage2Threads) k_energy_final(const double *p
 }
 
 // ---------------------------------------------------------------- rho and p
-
-// Energy density and pressure per site at the synchronised time (eq. rho-pres
-// in program units): rho = sum_i K_i + G_i + V_pr, p = sum_i K_i - G_i/3 - V_pr,
-// K_i = (v_i - r (a'/a) f_i)^2/2, G_i = a^(-2s-2) grad2(f_i)/2 with grad2 the
-// gradient energy density of the stencil (forward differences |d+ f|^2 for 7
-// points).  FP64 per site; rho, p may be NULL.  Partials: sum rho, sum p.
-template <typename T, typename To, int ST>
-__global__ void __launch_bounds__(256) k_rho_p(const T *__restrict__ d1, const T *__restrict__ d2,
-                                               const T *__restrict__ e1, const T *__restrict__ e2,
-                                               int N, const DevParams *__restrict__ P,
-                                               const DevScalars *__restrict__ S, To *rho, To *pr,
-                                               double *part)
-{
-    const int64_t N3 = (int64_t)N * N * N;
-    const double h = 0.5 * P->dt, r = P->r, s = P->s;
-    const double ak = S->a_half - h * S->ad, hub = S->ad / ak;
-    const double gs1 = S->bg_f[0] - h * S->bg_v[0], gs2 = S->bg_f[1] - h * S->bg_v[1];
-    const double vb1 = S->bg_v[0], vb2 = S->bg_v[1];
-    const double gfac = 0.5 * pow(ak, -2.0 * s - 2.0) * P->gw / (P->dx * P->dx);
-    const double cv1 = P->c1 * pow(ak, P->p1) / (double)P->beta, cv2 = 0.5 * P->G * pow(ak, P->p2);
-    const int beta = P->beta;
-    double acc[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const Wrap w(i, N);
-        auto sy1 = [&](int dx, int dy, int dz) {
-            const int64_t j = w(dx, dy, dz);
-            return (double)d1[j] - h * (double)e1[j];
-        };
-        auto sy2 = [&](int dx, int dy, int dz) {
-            const int64_t j = w(dx, dy, dz);
-            return (double)d2[j] - h * (double)e2[j];
-        };
-        const double s1 = (double)d1[i] - h * (double)e1[i];
-        const double s2 = (double)d2[i] - h * (double)e2[i];
-        const double x1 = gs1 + s1, x2 = gs2 + s2;
-        const double q1 = (vb1 + (double)e1[i]) - r * hub * x1;
-        const double q2 = (vb2 + (double)e2[i]) - r * hub * x2;
-        double g = grad_raw<ST>(sy1, s1);
-        g += grad_raw<ST>(sy2, s2);
-        const double K = 0.5 * (q1 * q1 + q2 * q2), Gs = gfac * g;
-        const double V = cv1 * ipow_d(x1, beta) + cv2 * x1 * x1 * x2 * x2;
-        const double rr = K + Gs + V, pp = K - Gs / 3.0 - V;
-        if (rho) rho[i] = (To)rr;
-        if (pr) pr[i] = (To)pp;
-        acc[0] += rr;
-        acc[1] += pp;
-    }
-    block_sum_store<2>(acc, part + (size_t)blockIdx.x * 2);
-}
 
 __global__ void __launch_bounds__(kStage2Threads) k_rho_p_final(const double *part, int nblk,
                                                                 const DevParams *__restrict__ P, double *out)
@@ -592,25 +657,50 @@ void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st)
     hipLaunchKernelGGL(k_aupdate_ens, dim3(R), dim3(kStage2Threads), 0, st, tab);
 }
 
-template <typename T, int ST>
-static void energy_t(const void *const s4[4], int N, const DevParams *P, const DevScalars *S, double *part,
-                     int nblk, hipStream_t st)
+// Launch shape of k_diag_march for an N^3 lattice: tiles of 64 x 4, z-chunks
+// chosen so that the items fill about `rows` blocks; grid = min(items, rows).
+struct DiagShape {
+    int ntx, nty, zchunk, items, grid;
+};
+
+static DiagShape diag_shape(int N, int rows)
 {
-    hipLaunchKernelGGL((k_energy_part<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0],
-                       (const T *)s4[1], (const T *)s4[2], (const T *)s4[3], N, P, S, part);
+    DiagShape d;
+    d.ntx = (N + kDiagX - 1) / kDiagX;
+    d.nty = (N + kDiagY - 1) / kDiagY;
+    const int tiles = d.ntx * d.nty;
+    int nz = rows / tiles;
+    nz = nz < 1 ? 1 : (nz > N ? N : nz);
+    d.zchunk = (N + nz - 1) / nz;
+    nz = (N + d.zchunk - 1) / d.zchunk;
+    d.items = tiles * nz;
+    d.grid = d.items < rows ? d.items : rows;
+    return d;
+}
+
+template <typename T, int ST, int MODE, typename To>
+static int diag_t(const void *const s4[4], int N, const DevParams *P, const DevScalars *S, To *rho, To *pr,
+                  double *part, int rows, hipStream_t st)
+{
+    const DiagShape d = diag_shape(N, rows);
+    hipLaunchKernelGGL((k_diag_march<T, ST, MODE, To>), dim3(d.grid), dim3(256), 0, st, (const T *)s4[0],
+                       (const T *)s4[1], (const T *)s4[2], (const T *)s4[3], N, d.zchunk, d.ntx, d.nty, d.items,
+                       P, S, rho, pr, part);
+    return d.grid;
 }
 
 void launch_energy(int stencil, int dtype, const void *const s4[4], int N, const DevParams *P,
                    const DevScalars *S, double *part, int nblk, double *out_dev, hipStream_t st)
 {
+    int g;
     if (stencil == 27) {
-        if (dtype == 0) energy_t<float, 27>(s4, N, P, S, part, nblk, st);
-        else energy_t<double, 27>(s4, N, P, S, part, nblk, st);
+        if (dtype == 0) g = diag_t<float, 27, 0, float>(s4, N, P, S, nullptr, nullptr, part, nblk, st);
+        else g = diag_t<double, 27, 0, float>(s4, N, P, S, nullptr, nullptr, part, nblk, st);
     } else {
-        if (dtype == 0) energy_t<float, 7>(s4, N, P, S, part, nblk, st);
-        else energy_t<double, 7>(s4, N, P, S, part, nblk, st);
+        if (dtype == 0) g = diag_t<float, 7, 0, float>(s4, N, P, S, nullptr, nullptr, part, nblk, st);
+        else g = diag_t<double, 7, 0, float>(s4, N, P, S, nullptr, nullptr, part, nblk, st);
     }
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, out_dev);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kStage2Threads), 0, st, part, g, P, S, out_dev);
 }
 
 template <typename T, typename To>
@@ -632,32 +722,25 @@ void launch_get_fields(int dtype, int out_dtype, const void *const s4[4], void *
     else get_fields_t<double, double>(s4, out, N, P, S, synchronized, st);
 }
 
-template <typename T, typename To, int ST>
-static void rho_p_t(const void *const s4[4], void *rho, void *pr, int N, const DevParams *P,
-                    const DevScalars *S, double *part, int nblk, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_rho_p<T, To, ST>), dim3(nblk), dim3(256), 0, st, (const T *)s4[0],
-                       (const T *)s4[1], (const T *)s4[2], (const T *)s4[3], N, P, S, (To *)rho, (To *)pr,
-                       part);
-}
-
 template <int ST>
-static void rho_p_s(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
-                    const DevParams *P, const DevScalars *S, double *part, int nblk, hipStream_t st)
+static int rho_p_s(int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
+                   const DevParams *P, const DevScalars *S, double *part, int nblk, hipStream_t st)
 {
-    if (dtype == 0 && out_dtype == 0) rho_p_t<float, float, ST>(s4, rho, pr, N, P, S, part, nblk, st);
-    else if (dtype == 0) rho_p_t<float, double, ST>(s4, rho, pr, N, P, S, part, nblk, st);
-    else if (out_dtype == 0) rho_p_t<double, float, ST>(s4, rho, pr, N, P, S, part, nblk, st);
-    else rho_p_t<double, double, ST>(s4, rho, pr, N, P, S, part, nblk, st);
+    if (dtype == 0 && out_dtype == 0)
+        return diag_t<float, ST, 1, float>(s4, N, P, S, (float *)rho, (float *)pr, part, nblk, st);
+    if (dtype == 0) return diag_t<float, ST, 1, double>(s4, N, P, S, (double *)rho, (double *)pr, part, nblk, st);
+    if (out_dtype == 0)
+        return diag_t<double, ST, 1, float>(s4, N, P, S, (float *)rho, (float *)pr, part, nblk, st);
+    return diag_t<double, ST, 1, double>(s4, N, P, S, (double *)rho, (double *)pr, part, nblk, st);
 }
 
 void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4], void *rho, void *pr, int N,
                   const DevParams *P, const DevScalars *S, double *part, int nblk, double *out_dev,
                   hipStream_t st)
 {
-    if (stencil == 27) rho_p_s<27>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
-    else rho_p_s<7>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
-    hipLaunchKernelGGL(k_rho_p_final, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, out_dev);
+    const int g = stencil == 27 ? rho_p_s<27>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st)
+                                : rho_p_s<7>(dtype, out_dtype, s4, rho, pr, N, P, S, part, nblk, st);
+    hipLaunchKernelGGL(k_rho_p_final, dim3(1), dim3(kStage2Threads), 0, st, part, g, P, out_dev);
 }
 
 void launch_sync_deviation(int dtype, const void *d, const void *e, double *out, int N, double h, int velocity,

@@ -20,6 +20,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -27,13 +28,21 @@ ROOT = os.path.dirname(PKG)
 COPY_MIB = 1024
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace runs collapsed, so
+    that editing a comment does not change the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def sweep_source_hash(stencil: int = 7) -> str:
-    """Hash of the sources of the sweep kernel of this stencil."""
+    """Hash of the code (comments aside) of the sweep kernel of this stencil."""
     h = hashlib.sha256()
     main = "lf_sweep27.hip" if stencil == 27 else "lf_sweep.hip"
     for f in (main, "lf_sweep_common.h", "lf_internal.h", "lf_stencil.h"):
-        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(PKG, "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
