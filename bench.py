@@ -31,9 +31,10 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(workload: str, stencil: int):
+def measured_traffic(workload: str, stencil: int, shape: dict):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on a different sweep source."""
+    or None when it is missing or was taken on a different sweep source or
+    launch shape."""
     from paper_0911_5692_amd.profile_sweep import sweep_source_hash
     path = os.path.join(ROOT, "profiles", f"sweep_traffic_{workload}.json")
     try:
@@ -41,7 +42,7 @@ def measured_traffic(workload: str, stencil: int):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("sweep_source_hash") != sweep_source_hash(stencil):
+    if d.get("sweep_source_hash") != sweep_source_hash(stencil) or d.get("launch_shape") != shape:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -257,7 +258,7 @@ def main() -> int:
     sweep_ms = kms[1]
     alg_bytes = 8 * esize * w.sites  # read f, v; write v, f_new; two fields
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, w.stencil)
+    traffic = measured_traffic(w.name, w.stencil, shape)
     log(f"kernel ms: a-update {kms[0]:.4f}, sweep {sweep_ms:.4f}, reduce {kms[2]:.4f}; "
         f"sweep {achieved:.0f} GB/s")
     lat.close()

@@ -56,16 +56,22 @@ struct Shape {
 // 7 or 27 (lf_params.stencil 0 means 7).
 int stencil_of(const lf_params *p) { return p->stencil == 27 ? 27 : 7; }
 
-int resident_blocks(const lf_params *p, int tile_x, int tile_y)
+int cu_count()
 {
     int dev = 0, cus = 0;
-    int per_cu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        per_cu = sweep_lds_blocks_per_cu(stencil_of(p), p->dtype, tile_x, tile_y, p->beta);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
     (void)hipGetLastError();
-    if (per_cu <= 0 || cus <= 0) return 3 * 256;
-    return per_cu * cus;
+    return cus > 0 ? cus : 256;
+}
+
+int resident_blocks(const lf_params *p, int tile_x, int tile_y)
+{
+    int per_cu = sweep_lds_blocks_per_cu(stencil_of(p), p->dtype, tile_x, tile_y, p->beta);
+    (void)hipGetLastError();
+    if (per_cu <= 0) per_cu = 3;
+    return per_cu * cu_count();
 }
 
 Shape shape_of(const lf_params *p)
@@ -91,11 +97,22 @@ Shape shape_of(const lf_params *p)
     if (p->zchunk) {
         sh.zchunk = p->zchunk < N ? p->zchunk : N;
     } else {
+        // The whole grid resident at once (tiles march in lockstep and find
+        // their neighbours' halo lines in L2).  The FP32 7-point sweep with
+        // 128-wide tiles does best with two blocks per CU: a smaller L2
+        // working set per XCD and long chunks (at 512^3: 256 planes, fetch
+        // 1.03x the algorithmic reads against 1.16x with three blocks per CU
+        // and 64 planes; 256^3: 32 planes).  The other sweeps fill the CUs
+        // and keep chunks of at most 64 planes.
+        const bool two_per_cu = stencil_of(p) == 7 && p->dtype == LF_F32 && sh.tile_x == 128;
         const int per_slab = ((N + sh.tile_x - 1) / sh.tile_x) * ((N + sh.tile_y - 1) / sh.tile_y);
-        int nzc = resident_blocks(p, sh.tile_x, sh.tile_y) / per_slab;
+        const int res = resident_blocks(p, sh.tile_x, sh.tile_y);
+        const int target = two_per_cu && 2 * cu_count() < res ? 2 * cu_count() : res;
+        int nzc = target / per_slab;
         nzc = nzc < 1 ? 1 : nzc;
         int dz = (N + nzc - 1) / nzc;
-        dz = dz < 8 ? 8 : (dz > 64 ? 64 : dz);
+        const int dz_max = two_per_cu ? N : 64;
+        dz = dz < 8 ? 8 : (dz > dz_max ? dz_max : dz);
         sh.zchunk = dz < N ? dz : N;
     }
     sh.rows = sweep_lds_blocks(N, sh.tile_x, sh.tile_y, sh.zchunk);
@@ -945,7 +962,7 @@ void cache_append(const char *path, const TuneKey &k, const lf_params *b, double
 }
 
 // Candidate launch shapes: the plain sweep, every LDS tile, and z-chunks from
-// the resident-grid choice, fixed depths and fractions of N.
+// the resident-grid choice, fixed depths and fractions of N (up to 46).
 int candidates(const lf_params *p, lf_params *out, int cap)
 {
     int n = 0;
@@ -954,9 +971,9 @@ int candidates(const lf_params *p, lf_params *out, int cap)
     out[n++] = q;
     const int tiles[5][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}};
     for (int t = 0; t < 5; ++t) {
-        const int zs[7] = {0, 16, 32, 64, 128, p->N / 4, p->N / 2};
-        int seen[8], ns = 0;
-        for (int j = 0; j < 7; ++j) {
+        const int zs[9] = {0, 16, 32, 64, 128, p->N / 6, p->N / 4, p->N / 3, p->N / 2};
+        int seen[9], ns = 0;
+        for (int j = 0; j < 9; ++j) {
             q = *p;
             q.tile_x = tiles[t][0];
             q.tile_y = tiles[t][1];

@@ -116,7 +116,8 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
     kf, kw = copy_bytes / fc, copy_bytes / wc
     fetch = sum(f_sweep) / len(f_sweep) * 1024.0 * kf
     write = sum(w_sweep) / len(w_sweep) * 1024.0 * kw
-    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(w.stencil), algorithmic_bytes_per_launch=alg,
+    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(w.stencil),
+               launch_shape=W.BENCH_SHAPES.get(w.name, {}), algorithmic_bytes_per_launch=alg,
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_calibration=kf, write_calibration=kw,
                fetch_over_algorithmic_reads=fetch / (alg / 2), write_over_algorithmic_writes=write / (alg / 2),
@@ -153,6 +154,7 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
         fh.write(f"| total HBM traffic | {(fetch + write) / 1e9:.4f} GB |\n")
         fh.write(f"| sweep launches averaged | {len(f_sweep)} |\n")
         fh.write(f"| sweep source hash | {res['sweep_source_hash']} |\n")
+        fh.write(f"| launch shape | {res['launch_shape']} |\n")
         if trace_dir:
             fh.write("\nKernel trace (rocprofv3 --kernel-trace --stats):\n\n| kernel | calls | avg ns | % |\n|---|---|---|---|\n")
             for k in res["kernel_stats"]:

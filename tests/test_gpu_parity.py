@@ -70,7 +70,7 @@ def test_cfg2_full_size_256_periodic_tiles():
 def test_cfg3_full_size_512_periodic_tiles():
     """512^3 FP32, 2000 steps: the benchmark's launch shape, against the oracle
     on the 64^3 period (same dx, dt)."""
-    _check(W.CFG3.resized(64), W.CFG3.steps, reps=8)
+    _check(W.CFG3.resized(64), W.CFG3.steps, reps=8, **W.BENCH_SHAPES[W.CFG3.name])
 
 
 @pytest.mark.parametrize("N", [4, 5, 7, 33, 100])
