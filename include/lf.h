@@ -257,8 +257,10 @@ int lf_adj_backward(lf_ctx *ctx, double dL, double *dL_dG, void *g_f1, void *g_f
  * with its own a(t), background and averages) and one persistent sweep whose
  * grid walks a static list of (realization, tile, z-chunk) work items.  The
  * sweep tile is per_real[0].tile_x/tile_y (default 64 x 8) for all
- * realizations; z-chunks may differ per realization (default N/2 planes,
- * at least 8, or N when N < 8).  Each realization's state matches a single-lattice run
+ * realizations; z-chunks may differ per realization (default: the whole
+ * lattice when the realizations' tile columns fill between half and all of
+ * the resident grid, else N/2 planes, at least 8, or N when N < 8).  Work
+ * items run longest chunk first.  Each realization's state matches a single-lattice run
  * with the same parameters to rounding. */
 int lf_ens_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
 int lf_ens_create(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,

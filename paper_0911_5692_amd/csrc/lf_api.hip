@@ -3,6 +3,7 @@
 #include "lf_internal.h"
 #include "../../include/lf.h"
 
+#include <algorithm>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -1098,13 +1099,27 @@ int ens_tile_x(const lf_params *p0) { return p0->tile_x ? p0->tile_x : 64; }
 // planes): two chunks per tile column.  On gfx950 that beat 16-64-plane
 // chunks for the mixed 64^3..160^3 ensemble by 5-8%, the fewer chunk-boundary
 // planes outweighing the smaller work list.
-lf_params ens_sub_params(const lf_params *pr, const lf_params *p0)
+// Default z-chunk of a realization: the whole lattice (one item per tile
+// column) when the ensemble's tile columns fill between half and all of the
+// resident grid, so that every item runs in a single round; otherwise half
+// the lattice (at least 8 planes).
+lf_params ens_sub_params(const lf_params *pr, const lf_params *p0, bool full_z)
 {
     lf_params q = *pr;
     q.tile_x = ens_tile_x(p0);
     q.tile_y = ens_tile_y(p0);
-    if (!q.zchunk) q.zchunk = pr->N / 2 > 8 ? pr->N / 2 : (pr->N < 8 ? pr->N : 8);
+    if (!q.zchunk) q.zchunk = full_z ? pr->N : (pr->N / 2 > 8 ? pr->N / 2 : (pr->N < 8 ? pr->N : 8));
     return q;
+}
+
+bool ens_full_z(int R, const lf_params *per)
+{
+    const int tx = ens_tile_x(&per[0]), ty = ens_tile_y(&per[0]);
+    long long cols = 0;
+    for (int r = 0; r < R; ++r) cols += (long long)((per[r].N + tx - 1) / tx) * ((per[r].N + ty - 1) / ty);
+    const lf_params q0 = ens_sub_params(&per[0], &per[0], false);
+    const long long grid = resident_blocks(&q0, tx, ty);
+    return 2 * cols >= grid && cols <= grid;
 }
 
 int ens_validate(int R, const lf_params *per)
@@ -1128,8 +1143,9 @@ size_t ens_layout(int R, const lf_params *per, size_t *sub_off, int *nitems)
 {
     size_t off = 0;
     int items = 0;
+    const bool full_z = ens_full_z(R, per);
     for (int r = 0; r < R; ++r) {
-        lf_params q = ens_sub_params(&per[r], &per[0]);
+        lf_params q = ens_sub_params(&per[r], &per[0], full_z);
         sub_off[r] = off;
         off = align_up(off + layout_of(&q).total);
         Shape sh = shape_of(&q);
@@ -1207,8 +1223,9 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     EnsEntry *htab = new EnsEntry[R];
     int4 *hitems = new int4[nitems > 0 ? nitems : 1];
     int k = 0;
+    const bool full_z = ens_full_z(R, per);
     for (int r = 0; r < R && rc == LF_OK; ++r) {
-        lf_params q = ens_sub_params(&per[r], &per[0]);
+        lf_params q = ens_sub_params(&per[r], &per[0], full_z);
         rc = lf_create(&q, stream, ws + so[r], so[r + 1] - so[r], &e->sub[r]);
         if (rc) break;
         lf_ctx *c = e->sub[r];
@@ -1230,6 +1247,10 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     }
     delete[] so;
     if (rc == LF_OK) {
+        // items with the most planes first: the persistent grid's last round
+        // is then made of the shortest items (each item keeps its partial row)
+        std::stable_sort(hitems, hitems + nitems,
+                         [&](const int4 &a, const int4 &b) { return htab[a.x].zchunk > htab[b.x].zchunk; });
         hipError_t he = hipMemcpyAsync(e->tab, htab, (size_t)R * sizeof(EnsEntry), hipMemcpyHostToDevice, e->stream);
         if (he == hipSuccess)
             he = hipMemcpyAsync(e->items, hitems, (size_t)nitems * sizeof(int4), hipMemcpyHostToDevice, e->stream);
@@ -1243,7 +1264,7 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
         return rc;
     }
     // persistent grid: as many blocks as fit on the device at once
-    const lf_params q0 = ens_sub_params(&per[0], &per[0]);
+    const lf_params q0 = ens_sub_params(&per[0], &per[0], false);
     int res = resident_blocks(&q0, e->tile_x, e->tile_y);
     e->grid = nitems < res ? nitems : res;
     *out = e;
