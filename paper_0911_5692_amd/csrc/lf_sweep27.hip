@@ -32,8 +32,12 @@
 // Per site the squared differences are summed by bond type in the working
 // precision and the weighted site sum 14 F + 3 E + C is accumulated in FP64.
 //
-// LDS per block (FP32, 128 x 8 tile): two staged planes of (TX+4)(TY+3) and
-// three new-value planes of (TX+2)(TY+1), both fields: 51 KB, 3 blocks/CU.
+// LDS per block: three staged planes of (TX+4)(TY+3) and three new-value
+// planes of (TX+2)(TY+1), both fields (FP32: 32 KB for the 64 x 8 tile, 62 KB
+// for 128 x 8).  With three buffers each, the loop is written out per phase
+// of the rotation, so LDS addresses are loop-invariant registers plus
+// immediate offsets and the register queues need no moves inside a period
+// (17% fewer VALU instructions per site than a runtime buffer index).
 #include "lf_sweep_common.h"
 
 #include <type_traits>
@@ -72,10 +76,11 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     constexpr int NRING = TX + 2 + TY;           // row y0-1 (x0-1 .. x0+TX), column x0-1 (y0 ..)
     constexpr int NHALO = 2 * (TX + 4) + 3 * TY + 2;
     static_assert(256 % TX == 0 && TY % RPR == 0 && NRING <= 256 && NHALO <= 512, "tile shape");
-    // staged planes: plane z+1 is read from sd[cur] while z+2 is written to
-    // sd[cur ^ 1]; new values: three planes in rotation (z, z-1 read after
-    // the barrier while the next iteration writes the third)
-    __shared__ T sd[2][2][LH * LW];
+    // staged planes: plane z+1 is read from one buffer while z+2 is written
+    // to the next; new values: plane z written, z-1 read after the barrier.
+    // Both rotate over three buffers, so that three iterations bring every
+    // buffer index back (see step below)
+    __shared__ T sd[3][2][LH * LW];
     __shared__ T sn[3][2][NHT * NW];
 
     Coefs<T, NH> c;
@@ -216,8 +221,6 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     }
 
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int cur = 0;
-    int nb_cur = 0, nb_prev = 2;  // new-value planes of z and z-1
     // The new values of plane z are stored at the top of iteration z+1, just
     // before its loads.  The memory counter retires in issue order, so the
     // wait for those loads at the end of the iteration then finds stores that
@@ -240,7 +243,14 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
                 }
         }
     };
-    for (int z = zs; z < z1; ++z) {
+    // One iteration at phase PH of the buffer rotation: staged plane sd[PH]
+    // (plane z+2 goes to sd[(PH + 1) % 3]), new-value planes sn[PH] (plane z)
+    // and sn[(PH + 2) % 3] (plane z-1).
+    // The phase is a compile-time constant, so every LDS address is a
+    // loop-invariant register plus an immediate offset.
+    auto step = [&](auto phase, const int z) __attribute__((always_inline)) {
+        constexpr int PH = decltype(phase)::value;
+        constexpr int cur = PH, nxt = (PH + 1) % 3, nb_cur = PH, nb_prev = (PH + 2) % 3;
         flush();
         // loads for the next iteration: d(z+3), halo(z+3), e(z+1)
         {
@@ -318,7 +328,7 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         // past z1 the registers repeat a clamped plane and the buffer is not
         // read again)
         {
-            T *t0 = sd[cur ^ 1][0], *t1 = sd[cur ^ 1][1];
+            T *t0 = sd[nxt][0], *t1 = sd[nxt][1];
 #pragma unroll
             for (int k = 0; k < KI; ++k) { t0[lsd[k]] = nd1[k]; t1[lsd[k]] = nd2[k]; }
             if (hasr) { t0[rlsd] = rnd1; t1[rlsd] = rnd2; }
@@ -386,9 +396,18 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         for (int m = 0; m < 2; ++m) { hv1[m] = lh1[m]; hv2[m] = lh2[m]; }
         pend = live;
         pz_st = z;
-        cur ^= 1;
-        nb_prev = nb_cur;
-        nb_cur = nb_cur == 2 ? 0 : nb_cur + 1;
+    };
+    // three iterations (a full rotation period) per trip, then up to two more
+    using std::integral_constant;
+    int z = zs;
+    for (; z + 3 <= z1; z += 3) {
+        step(integral_constant<int, 0>{}, z);
+        step(integral_constant<int, 1>{}, z + 1);
+        step(integral_constant<int, 2>{}, z + 2);
+    }
+    if (z < z1) {
+        step(integral_constant<int, 0>{}, z);
+        if (z + 1 < z1) step(integral_constant<int, 1>{}, z + 1);
     }
 
     flush();
@@ -421,7 +440,7 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
 template <typename T, int TX, int TY>
 constexpr int sweep27_waves()
 {
-    constexpr int lds = (int)sizeof(T) * (2 * 2 * (TY + 3) * (TX + 4) + 3 * 2 * (TY + 1) * (TX + 2));
+    constexpr int lds = (int)sizeof(T) * (3 * 2 * (TY + 3) * (TX + 4) + 3 * 2 * (TY + 1) * (TX + 2));
     constexpr int by_lds = 160 * 1024 / lds;
     constexpr int by_regs = sizeof(T) == 4 ? LF_SWEEP27_MIN_WAVES : 2;
     return by_lds < by_regs ? (by_lds < 1 ? 1 : by_lds) : by_regs;
