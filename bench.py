@@ -93,6 +93,30 @@ def time_extras(w, dtype) -> tuple[dict, dict]:
     return init, spectrum
 
 
+def copy_reference(N: int, reps: int = 20) -> dict:
+    """Rate of lf_stream_copy over the sweep's bytes at N^3 (four FP32 arrays
+    read, four written, no arithmetic): what the device streams for this
+    read/write mix, timed with HIP events on the current stream."""
+    import torch
+
+    from paper_0911_5692_amd import stream_copy
+
+    src = [torch.zeros(N ** 3, dtype=torch.float32, device="cuda:0") for _ in range(4)]
+    dst = [torch.empty_like(src[0]) for _ in range(4)]
+    for _ in range(3):
+        stream_copy(src, dst)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        stream_copy(src, dst)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del src, dst
+    return {"kernel": "lf_stream_copy (16-byte loads, non-temporal 16-byte stores)", "bytes": 32 * N ** 3,
+            "ms": round(ms, 5), "GBps": round(32 * N ** 3 / (ms * 1e-3) / 1e9, 1)}
+
+
 def time_additions() -> dict:
     """Measured numbers of the rows and additions beyond the step itself:
     rho/p per site at 512^3 (algorithmic 16 B read + 8 B written per site,
@@ -207,8 +231,8 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU z-slab path is a design "
-              "(see DESIGN.md), not an implementation. Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the multi-GPU z-slab path is a design, not an "
+              "implementation. Run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
@@ -263,6 +287,11 @@ def main() -> int:
         f"sweep {achieved:.0f} GB/s")
     lat.close()
     torch.cuda.synchronize()
+    copy = None
+    if w.dtype == "f32":
+        copy = copy_reference(w.N)
+        copy["sweep_frac_of_copy"] = round(achieved / copy["GBps"], 4)
+        log(f"stream copy of the same bytes: {copy}")
 
     init = spectrum = None
     if not args.no_init_timing:
@@ -310,7 +339,8 @@ def main() -> int:
                      "traffic": traffic,
                      "kernel": "k_sweep_lds27 (fused kick-drift, 27-point)" if w.stencil == 27
                      else "k_sweep_lds (fused kick-drift, 7-point)",
-                     "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes},
+                     "kernel_ms": round(sweep_ms, 5), "bytes_per_launch": alg_bytes,
+                     "copy_reference": copy},
         "cpu_baseline": cpu,
         "init": init,
         "spectrum": spectrum,

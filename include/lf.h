@@ -208,6 +208,20 @@ int lf_set_coupling(lf_ctx *ctx, double G);
  * enqueued, in ms (blocking; 0 if none). */
 int lf_last_step_ms(lf_ctx *ctx, double *ms);
 
+/* ---- bandwidth reference ------------------------------------------------ */
+
+/* Copy four FP32 arrays of n elements into four others (b_j = a_j): the byte
+ * mix of the FP32 sweep (16 B read and 16 B written per element index) with
+ * 16-byte loads and non-temporal 16-byte stores over a grid-stride loop.  It
+ * does no arithmetic, so its rate is what the device streams for this mix;
+ * the benchmark reports the sweep's bandwidth as a fraction of it.
+ * Pointers: device arrays, 256-byte aligned, caller-owned, not overlapping;
+ * n >= 0 and a multiple of 4 (n = 0 does nothing and checks no pointer).
+ * Asynchronous on `stream` (LF_EINVAL for bad arguments, LF_EHIP if the
+ * launch fails). */
+int lf_stream_copy(const float *a0, const float *a1, const float *a2, const float *a3, float *b0, float *b1,
+                   float *b2, float *b3, int64_t n, void *stream);
+
 /* ---- autotuner ---------------------------------------------------------- */
 
 /* Workspace for lf_autotune with these parameters (largest candidate). */

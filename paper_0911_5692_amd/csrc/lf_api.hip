@@ -586,6 +586,22 @@ int lf_set_coupling(lf_ctx *c, double G)
     return LF_OK;
 }
 
+int lf_stream_copy(const float *a0, const float *a1, const float *a2, const float *a3, float *b0, float *b1,
+                   float *b2, float *b3, int64_t n, void *stream)
+{
+    if (n < 0 || n % 4) return fail(LF_EINVAL, "n=%lld: must be >= 0 and a multiple of 4", (long long)n);
+    if (n == 0) return LF_OK;
+    const float *a[4] = {a0, a1, a2, a3};
+    float *b[4] = {b0, b1, b2, b3};
+    const char *an[4] = {"a0", "a1", "a2", "a3"}, *bn[4] = {"b0", "b1", "b2", "b3"};
+    int rc;
+    for (int j = 0; j < 4; ++j)
+        if ((rc = check_ptr(a[j], an[j])) || (rc = check_ptr(b[j], bn[j]))) return rc;
+    launch_stream_copy(a, b, n, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return LF_OK;
+}
+
 int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
 {
     if (!c || !ms) return fail(LF_EINVAL, "NULL argument");

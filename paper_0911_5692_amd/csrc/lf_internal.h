@@ -112,6 +112,7 @@ void launch_rho_p(int stencil, int dtype, int out_dtype, const void *const s4[4]
 void launch_get_fields(int dtype, int out_dtype, const void *const st4[4], void *const out[4],
                        int N, const DevParams *P, const DevScalars *S, int synchronized,
                        hipStream_t st);
+void launch_stream_copy(const float *const a[4], float *const b[4], int64_t n, hipStream_t st);
 void launch_sync_deviation(int dtype, const void *d, const void *e, double *out, int N, double h, int velocity,
                            hipStream_t st);
 void launch_sum_partials(const double *part, int nblk, int nv, double *out, hipStream_t st);

@@ -80,6 +80,21 @@ def vacuum_fields(N: int, L: float, spec: dict, device="cuda", stream: torch.cud
     return tuple(out)
 
 
+def stream_copy(src, dst, stream: torch.cuda.Stream | None = None) -> None:
+    """dst[j] = src[j] for four contiguous float32 tensors of one size
+    (lf_stream_copy, the bandwidth reference of the benchmark); asynchronous
+    on `stream` (default: the current stream)."""
+    if len(src) != 4 or len(dst) != 4:
+        raise ValueError("four source and four destination tensors")
+    n = src[0].numel()
+    for t in (*src, *dst):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("contiguous float32 device tensors of one size")
+    st = stream or torch.cuda.current_stream(src[0].device)
+    check(lib().lf_stream_copy(*(ctypes.c_void_p(t.data_ptr()) for t in (*src, *dst)), int(n),
+                               ctypes.c_void_p(st.cuda_stream)))
+
+
 def _aligned(t: torch.Tensor) -> torch.Tensor:
     return t if (t.is_contiguous() and t.data_ptr() % 256 == 0) else t.contiguous().clone()
 

@@ -137,3 +137,14 @@ def test_spectrum_arguments_checked_before_any_device_call(LB):
     buf = (ctypes.c_double * 8)()
     assert lib.lf_spectrum(None, 0, 4, buf, buf, ctypes.c_void_p(0x100000), 1 << 20) == LB.LF_EINVAL
     assert "ctx" in lib.lf_last_error().decode()
+
+
+def test_stream_copy_arguments_checked_before_any_device_call(LB):
+    lib = LB.lib()
+    p = ctypes.c_void_p(0x100000)  # aligned, never dereferenced: the checks come first
+    assert lib.lf_stream_copy(p, p, p, p, p, p, p, p, 6, None) == LB.LF_EINVAL
+    assert "multiple of 4" in lib.lf_last_error().decode()
+    assert lib.lf_stream_copy(p, p, p, p, p, p, p, None, 8, None) == LB.LF_EINVAL
+    assert "b3" in lib.lf_last_error().decode()
+    assert lib.lf_stream_copy(p, ctypes.c_void_p(0x100004), p, p, p, p, p, p, 8, None) == LB.LF_EINVAL
+    assert "a1" in lib.lf_last_error().decode()
