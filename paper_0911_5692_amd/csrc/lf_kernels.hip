@@ -228,20 +228,27 @@ __device__ void aupdate_block(const double *part, int nblk, const DevParams *__r
 {
     double t[kNPart];
     stage2_sum<kNPart>(part, nblk, t);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;
     const double N3 = P->N3, dx = P->dx, dt = P->dt, r = P->r, s = P->s;
     const double c1 = P->c1, G = P->G;
     const int beta = P->beta;
     const double a = S->a_half, w = S->ad;
-    const double ap1 = pow(a, P->p1), ap2 = pow(a, P->p2);
+    // the five powers of a, one per lane of the first wave, side by side
+    // instead of one after another on a single thread
+    const int l = threadIdx.x;
+    const double ex = l == 0 ? P->p1 : l == 1 ? P->p2 : l == 2 ? -2.0 * s - 2.0 * r - 1.0
+                    : l == 3 ? 2.0 * s + 2.0 : -2.0 * s - 2.0;
+    const double pw = pow(a, ex);
+    const double ap1 = __shfl(pw, 0, 64), ap2 = __shfl(pw, 1, 64), aF = __shfl(pw, 2, 64);
+    const double aV = __shfl(pw, 3, 64), alpha = __shfl(pw, 4, 64);
+    if (l != 0) return;
     const double Sg = P->gw * (t[0] + t[1]) / (dx * dx * N3);
     const double SV = (c1 * ap1 * t[2] / (double)beta + 0.5 * G * ap2 * t[3]) / N3;
-    const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
+    const double Fa = P->kappa2 * aF * (Sg / 3.0 + aV * SV);
     const double c = (-s - 2.0) * dt / (4.0 * a);
     const double disc = 1.0 - 8.0 * c * w - 4.0 * c * dt * Fa;
     const double u = 2.0 * (c * w * w + w + dt * Fa) / ((1.0 - 2.0 * c * w) + sqrt(disc));
     const double adh = 0.5 * (w + u), add = (u - w) / dt, an = a + dt * u;
-    const double alpha = pow(a, -2.0 * s - 2.0);
     const double bc = r * (s - r + 2.0) * (adh / a) * (adh / a) + r * add / a;
 
     // homogeneous mode: same kick and drift with zero Laplacian

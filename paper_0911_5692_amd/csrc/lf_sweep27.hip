@@ -130,7 +130,7 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     const bool hasr = t < NRING;
     const bool rrow = t < TX + 2;
     const int rlx = rrow ? t - 1 : -1, rly = rrow ? -1 : t - (TX + 2);
-    const unsigned roff = hasr ? (unsigned)(wrapc(y0 + rly) * N + wrapc(x0 + rlx)) * sizeof(T) : 0u;
+    unsigned roff = hasr ? (unsigned)(wrapc(y0 + rly) * N + wrapc(x0 + rlx)) * sizeof(T) : 0u;
     const int rlsd = hasr ? (rly + 2) * LW + rlx + 2 : 0;
     const int rlsn = hasr ? (rly + 1) * NW + rlx + 1 : 0;
     // the ring's bonds into the interior: three to plane z-1 (index rq,
@@ -251,6 +251,13 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     auto step = [&](auto phase, const int z) __attribute__((always_inline)) {
         constexpr int PH = decltype(phase)::value;
         constexpr int cur = PH, nxt = (PH + 1) % 3, nb_cur = PH, nb_prev = (PH + 2) % 3;
+        // the byte offsets pass through an empty asm once per iteration, so
+        // the compiler forms each address as SGPR plane base + this VGPR
+        // (no 64-bit address arithmetic per access)
+#pragma unroll
+        for (int k = 0; k < KI; ++k) asm volatile("" : "+v"(goff[k]));
+        asm volatile("" : "+v"(roff));
+        asm volatile("" : "+v"(hoff[0]), "+v"(hoff[1]));
         flush();
         // loads for the next iteration: d(z+3), halo(z+3), e(z+1)
         {
