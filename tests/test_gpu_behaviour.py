@@ -212,3 +212,32 @@ def test_history_series_matches_oracle(stencil):
         assert abs(h["rho"][j] - e["rho"]) <= 1e-10 * e["rho"]
         assert abs(h["R"][j] - e["R"]) <= 1e-12
         assert abs(h["w"][j] - avg["w"]) <= 1e-10 * max(1.0, abs(avg["w"]))
+
+
+@pytest.mark.parametrize("stencil", [7, 27])
+def test_rho_p_and_energies_full_size_512_periodic(stencil):
+    """512^3 in the benchmark's launch shape with a 64^3-periodic state: the
+    per-site rho and p (FP32 out) repeat bitwise with the period and equal the
+    oracle's 64^3 values; the averages and the energies equal the oracle's."""
+    from dataclasses import replace
+    base = replace(W.CFG3, stencil=stencil)
+    w = base.resized(64)
+    shape = W.BENCH_SHAPES[W.CFG3_S27.name if stencil == 27 else W.CFG3.name]
+    log(f"[rho_p 512] stencil={stencil} shape={shape}")
+    st, en, _, ic = oracle_run(w, 40)
+    rho, p, avg = O.rho_p(st)
+    lat, _ = gpu_run(w, ic, 40, dtype="f32", reps=8, **shape)
+    grho, gp, gavg = lat.rho_p(dtype=torch.float32)
+    for name, g, ref in (("rho", grho, rho), ("p", gp, p)):
+        t = g.view(8, 64, 8, 64, 8, 64)
+        assert bool((t == t[0:1, :, 0:1, :, 0:1, :]).all()), f"periodic copies of {name} differ"
+        first = g[:64, :64, :64].double().cpu().numpy()
+        err = float(np.max(np.abs(first - ref)) / np.max(np.abs(ref)))
+        log(f"[rho_p 512] {name} rel err {err:.2e}")
+        assert err <= 1e-5, (name, err)
+    for k in ("rho", "p", "w"):
+        assert abs(gavg[k] - avg[k]) <= 1e-5 * abs(avg[k]), (k, gavg[k], avg[k])
+    g = lat.energies()
+    for k in ("K1", "K2", "G1", "G2", "P", "rho"):
+        assert abs(g[k] - en[k]) <= 1e-5 * abs(en[k]), k
+    lat.close()
