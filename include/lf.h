@@ -91,7 +91,10 @@ typedef struct lf_params {
     double kappa2;    /* 8 pi G_Newton / A^2 (0 = no expansion) */
     int32_t tile_y;   /* sweep tile rows: 0 = automatic, 1 = plain one-site-per-thread
                          sweep with a separate reduction, 4, 8 or 16 = LDS z-march */
-    int32_t zchunk;   /* planes per z-chunk of the LDS sweep, 0 = automatic */
+    int32_t zchunk;   /* planes per z-chunk of the LDS sweep, 0 = automatic (a grid that
+                         is resident at once: two blocks per CU for the FP32 7-point
+                         sweep with 128-wide tiles, else as many as fit, with chunks
+                         of at most 64 planes) */
     int32_t tile_x;   /* sweep tile columns: 0 = automatic, 64 or 128 (128 with
                          tile_y 4 or 8 only) */
     int32_t stencil;  /* Laplacian: 0 or 7 = 7-point, 27 = 27-point (see above) */
@@ -227,11 +230,12 @@ int lf_stream_copy(const float *a0, const float *a1, const float *a2, const floa
 /* Workspace for lf_autotune with these parameters (largest candidate). */
 int lf_autotune_workspace_bytes(const lf_params *p, size_t *out_bytes);
 /* Pick the sweep launch shape (tile_x, tile_y, zchunk) for p's lattice size,
- * dtype and beta on the current device.  If cache_path (may be NULL) holds a
- * line for (device architecture, N, dtype, beta), that choice is returned
- * (*best_ms = -1).  Otherwise every candidate (the plain sweep; LDS tiles
- * 64x4, 64x8, 64x16, 128x4, 128x8; z-chunks from the resident-grid rule, 16,
- * 32, 64, 128, N/4, N/2) is timed with HIP events over graph-replayed steps
+ * dtype, beta and stencil on the current device.  If cache_path (may be
+ * NULL) holds a line for (device architecture, N, dtype, beta, stencil), that
+ * choice is returned (*best_ms = -1).  Otherwise every candidate (the plain
+ * sweep; LDS tiles 64x4, 64x8, 64x16, 128x4, 128x8; z-chunks from the
+ * automatic rule, 16, 32, 64, 128, N/6, N/4, N/3, N/2) is timed with HIP
+ * events over graph-replayed steps
  * of a synthetic state, the fastest is returned in *best (p with the shape
  * filled in) and appended to the cache as one JSON object per line.  The
  * caller's workspace (lf_autotune_workspace_bytes) is overwritten. */
