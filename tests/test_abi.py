@@ -50,6 +50,12 @@ def test_abi_version_and_workspace(LB):
     s64 = ctypes.c_size_t()
     assert lib.lf_workspace_bytes(ctypes.byref(_params(LB, dtype=1)), ctypes.byref(s64)) == 0
     assert s64.value > size.value
+    # the size limits: N = 4 and N = 2048 (8 FP32 arrays of 2048^3: 275 GB) are
+    # accepted, N = 2049 is not
+    for n in (4, 2048):
+        assert lib.lf_workspace_bytes(ctypes.byref(_params(LB, N=n)), ctypes.byref(size)) == 0
+        assert size.value >= 8 * n ** 3 * 4
+    assert lib.lf_workspace_bytes(ctypes.byref(_params(LB, N=2049)), ctypes.byref(size)) == LB.LF_EINVAL
 
 
 @pytest.mark.parametrize("kw,frag", [
