@@ -16,11 +16,11 @@
 // Two implementations of the same per-site arithmetic (identical rounding):
 //
 // k_sweep_lds — the production kernel.  A block of 256 threads owns a
-//   64 (x) x TY (y) column tile and marches a chunk of z planes.  Each plane
-//   of d1, d2 is staged in LDS with its halo (the paper's "three shared
-//   planes" become one LDS plane plus a register queue d(z-1), d(z), d(z+1)
-//   per site); x rows are 64 consecutive elements, so every global access is
-//   a coalesced 256-byte row.  The sums the next scale-factor update needs
+//   TX (x, 64 or 128) x TY (y) column tile and marches a chunk of z planes.
+//   Each plane of d1, d2 is staged in LDS with its halo (the paper's "three
+//   shared planes" become one LDS plane plus a register queue d(z-1), d(z),
+//   d(z+1) per site); x rows are TX consecutive elements, so every global
+//   access is a coalesced 256- or 512-byte row.  The sums the next scale-factor update needs
 //   (sum |grad d_new|^2 per field, sum f1^beta, sum f1^2 f2^2 of the new
 //   fields) are formed in the same sweep: gradients use backward differences,
 //   and the block also computes d_new on a one-sided ring (row y0-1, column
