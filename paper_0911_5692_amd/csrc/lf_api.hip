@@ -210,12 +210,10 @@ struct lf_ctx {
 namespace {
 
 // One leapfrog step: FP64 scale-factor update from the pending partial sums,
-// then the fused kick-drift sweep from buffer `cur` into `cur ^ 1`, which
+// then the fused kick-drift sweep from the arrays `in` into `out`, which
 // leaves the partial sums of the new fields for the next step.
-void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
+void enqueue_step_io(lf_ctx *c, const void *const in[4], void *const out[4], hipStream_t st, hipEvent_t *ev)
 {
-    const void *in[4] = {c->buf[cur][0], c->buf[cur][1], c->buf[cur][2], c->buf[cur][3]};
-    void *out[4] = {c->buf[cur ^ 1][0], c->buf[cur ^ 1][1], c->buf[cur ^ 1][2], c->buf[cur ^ 1][3]};
     if (ev) (void)hipEventRecord(ev[0], st);
     launch_aupdate(c->part, c->sh.rows, c->P, c->S, c->C, st);
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -230,6 +228,14 @@ void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
         if (ev) (void)hipEventRecord(ev[2], st);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
+}
+
+// The step from the context's buffer `cur` into `cur ^ 1`.
+void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
+{
+    const void *in[4] = {c->buf[cur][0], c->buf[cur][1], c->buf[cur][2], c->buf[cur][3]};
+    void *out[4] = {c->buf[cur ^ 1][0], c->buf[cur ^ 1][1], c->buf[cur ^ 1][2], c->buf[cur ^ 1][3]};
+    enqueue_step_io(c, in, out, st, ev);
 }
 
 int ensure_events(hipEvent_t *ev0, hipEvent_t *ev1)
@@ -675,16 +681,18 @@ int save_slot(lf_ctx *c, char *slot, const AdjLayout &L)
     return LF_OK;
 }
 
-int restore_slot(lf_ctx *c, const char *slot, const AdjLayout &L)
+// Checkpoint `slot` back: its four arrays into `arrays` (4 x arr_bytes apart),
+// its scalars and pending sums into the context.
+int restore_slot(lf_ctx *c, const char *slot, char *arrays, const AdjLayout &L)
 {
     const size_t bytes = (size_t)c->p.N * c->p.N * c->p.N * esize(c->p.dtype);
     for (int j = 0; j < 4; ++j)
-        HIPCHK(hipMemcpyAsync(c->buf[0][j], slot + j * L.arr_bytes, bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(arrays + j * L.arr_bytes, slot + j * L.arr_bytes, bytes, hipMemcpyDeviceToDevice,
+                              c->stream));
     const char *sc = slot + 4 * L.arr_bytes;
     HIPCHK(hipMemcpyAsync(c->S, sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
     launch_set_pending(c->part, c->sh.rows, (const double *)(sc + align_up(sizeof(DevScalars))), c->stream);
     HIPCHK(hipGetLastError());
-    c->cur = 0;
     return LF_OK;
 }
 
@@ -757,18 +765,22 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
     launch_adj_seed(stencil_of(&c->p), c->p.dtype, s4, c->p.N, c->P, c->S, wd, lam[0], part, kRedBlocks, A, c->stream);
     HIPCHK(hipGetLastError());
     int li = 0;
-    const size_t bytes = n3 * esize(c->p.dtype);
     DevScalars *tape = (DevScalars *)(ws + L.tape);
     for (int64_t s = L.nck - 1; s >= 0; --s) {
-        if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, L))) return rc;
+        // recompute the segment: segment slot j receives the state before
+        // step j (the sweep of step j - 1 writes it there directly) and the
+        // tape the scalars before step j; the segment's last step is not
+        // needed
+        if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, ws + L.seg, L))) return rc;
         const int64_t m = (n - s * K) < K ? (n - s * K) : K;
         for (int64_t j = 0; j < m; ++j) {
-            char *dst = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
-            for (int q = 0; q < 4; ++q)
-                HIPCHK(hipMemcpyAsync(dst + q * L.arr_bytes, c->buf[c->cur][q], bytes, hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
-            enqueue_step(c, c->cur, c->stream, nullptr);
-            c->cur ^= 1;
+            if (j + 1 < m) {
+                char *a = ws + L.seg + (size_t)j * 4 * L.arr_bytes, *b = a + 4 * L.arr_bytes;
+                const void *in[4] = {a, a + L.arr_bytes, a + 2 * L.arr_bytes, a + 3 * L.arr_bytes};
+                void *out[4] = {b, b + L.arr_bytes, b + 2 * L.arr_bytes, b + 3 * L.arr_bytes};
+                enqueue_step_io(c, in, out, c->stream, nullptr);
+            }
         }
         for (int64_t j = m - 1; j >= 0; --j) {
             const char *src = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
