@@ -198,23 +198,44 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
 {
     double R[7];
     stage2<7>(part, nblk, R);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;
     const double n3 = P->N3, dx = P->dx, dt = P->dt, r = P->r, s = P->s, c1 = P->c1, G = P->G;
     const int beta = P->beta;
     const double a = tape->a_half, w = tape->ad;
     const double p1 = P->p1, p2 = P->p2;
-    const double ap1 = pow(a, p1), ap2 = pow(a, p2);
-    const double dap1 = p1 * pow(a, p1 - 1.0), dap2 = p2 * pow(a, p2 - 1.0);
+    const double e1 = -2.0 * s - 2.0 * r - 1.0;
+    // the eleven powers of a, one per lane of the first wave, side by side
+    const int l = threadIdx.x;
+    double ex;
+    switch (l) {
+    case 0: ex = p1; break;
+    case 1: ex = p2; break;
+    case 2: ex = p1 - 1.0; break;
+    case 3: ex = p2 - 1.0; break;
+    case 4: ex = e1; break;
+    case 5: ex = 2.0 * s + 2.0; break;
+    case 6: ex = -2.0 * s - 2.0; break;
+    case 7: ex = -2.0 * s - 3.0; break;
+    case 8: ex = e1 + 2.0 * s + 2.0; break;
+    case 9: ex = e1 - 1.0; break;
+    default: ex = e1 + 2.0 * s + 1.0; break;
+    }
+    const double pw = pow(a, ex);
+    const double ap1 = __shfl(pw, 0, 64), ap2 = __shfl(pw, 1, 64);
+    const double pa_p1m = __shfl(pw, 2, 64), pa_p2m = __shfl(pw, 3, 64), pa_e1 = __shfl(pw, 4, 64);
+    const double pa_2s2 = __shfl(pw, 5, 64), alpha = __shfl(pw, 6, 64), pa_m2s3 = __shfl(pw, 7, 64);
+    const double pa_e1s = __shfl(pw, 8, 64), pa_e1m = __shfl(pw, 9, 64), pa_e1s1 = __shfl(pw, 10, 64);
+    if (l != 0) return;
+    const double dap1 = p1 * pa_p1m, dap2 = p2 * pa_p2m;
     // forward scalars of this step
     const double gw = P->gw;
     const double Sg = gw * R[6] / (dx * dx * n3);
     const double SV = (c1 * ap1 * R[4] / (double)beta + 0.5 * G * ap2 * R[5]) / n3;
-    const double Fa = P->kappa2 * pow(a, -2.0 * s - 2.0 * r - 1.0) * (Sg / 3.0 + pow(a, 2.0 * s + 2.0) * SV);
+    const double Fa = P->kappa2 * pa_e1 * (Sg / 3.0 + pa_2s2 * SV);
     const double c = (-s - 2.0) * dt / (4.0 * a);
     const double disc = 1.0 - 8.0 * c * w - 4.0 * c * dt * Fa;
     const double u = 2.0 * (c * w * w + w + dt * Fa) / ((1.0 - 2.0 * c * w) + sqrt(disc));
     const double adh = 0.5 * (w + u), add = (u - w) / dt;
-    const double alpha = pow(a, -2.0 * s - 2.0);
     const double rr = r * (s - r + 2.0);
     const double bc = rr * (adh / a) * (adh / a) + r * add / a;
     // kick sensitivities
@@ -226,7 +247,7 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     const double sdVdG = 0.5 * ap2 * R[5];
     const double la = A[0], lw = A[1];
     double ga = la + gak;
-    ga += galpha * (-2.0 * s - 2.0) * pow(a, -2.0 * s - 3.0);
+    ga += galpha * (-2.0 * s - 2.0) * pa_m2s3;
     const double g_adh = gbeta * 2.0 * rr * adh / (a * a);
     const double g_add = gbeta * r / a;
     ga += gbeta * (-2.0 * rr * adh * adh / (a * a * a) - r * add / (a * a));
@@ -237,10 +258,9 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     g_w += g_u * (1.0 + q) / hu;
     ga += g_u * (-(dt * (-s - 2.0) * (w + u) * (w + u) / (4.0 * a * a)) / hu);
     const double gF = g_u * dt / hu;
-    const double e1 = -2.0 * s - 2.0 * r - 1.0;
-    const double gSg = gF * P->kappa2 * pow(a, e1) / 3.0;
-    const double gSV = gF * P->kappa2 * pow(a, e1 + 2.0 * s + 2.0);
-    ga += gF * P->kappa2 * (e1 * pow(a, e1 - 1.0) * Sg / 3.0 + (e1 + 2.0 * s + 2.0) * pow(a, e1 + 2.0 * s + 1.0) * SV);
+    const double gSg = gF * P->kappa2 * pa_e1 / 3.0;
+    const double gSV = gF * P->kappa2 * pa_e1s;
+    ga += gF * P->kappa2 * (e1 * pa_e1m * Sg / 3.0 + (e1 + 2.0 * s + 2.0) * pa_e1s1 * SV);
     ga += gSV * sdVda / n3;
     A[0] = ga;
     A[1] = g_w;
