@@ -275,17 +275,25 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
 }
 
 // Pass B: field cotangents of X_k from those of X_{k+1} (in -> out).
-template <typename T, int ST>
+// NEXT: also pass A of the next reverse step (X_{k-1}: stored fields n1, n2,
+// scalars tape_n) over the cotangents just written, into part; launched on
+// the grid of k_adj_reduce, so every site meets the same thread and the
+// sums are bitwise those of a separate k_adj_reduce.
+template <typename T, int ST, bool NEXT>
 __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, const T *__restrict__ d2,
                                                     int N, int beta, const DevScalars *__restrict__ tape,
                                                     const double *__restrict__ cf,
                                                     const double *__restrict__ lf1, const double *__restrict__ lf2,
                                                     const double *__restrict__ lv1, const double *__restrict__ lv2,
-                                                    double *of1, double *of2, double *ov1, double *ov2)
+                                                    double *of1, double *of2, double *ov1, double *ov2,
+                                                    const T *__restrict__ n1, const T *__restrict__ n2,
+                                                    const DevScalars *__restrict__ tape_n, double *part)
 {
     const int64_t N3 = (int64_t)N * N * N;
     const double g1 = tape->bg_f[0], g2 = tape->bg_f[1];
     const double cl = cf[0], cb = cf[1], c1a = cf[2], Ga = cf[3], cSg = cf[4], cSV = cf[5], dt = cf[6];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const double gn1 = NEXT ? tape_n->bg_f[0] : 0.0, gn2 = NEXT ? tape_n->bg_f[1] : 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
          i += (int64_t)gridDim.x * blockDim.x) {
         const Wrap wr(i, N);
@@ -311,11 +319,31 @@ __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, co
         const double h22 = Ga * f1 * f1;
         const double dv1 = c1a * ipw(f1, beta - 1) + Ga * f1 * f2 * f2;
         const double dv2 = Ga * f1 * f1 * f2;
-        of1[i] = lf1[i] + cl * lm1 + cb * m1 - dt * (h11 * m1 + h12 * m2) + cSg * s1 + cSV * dv1;
-        of2[i] = lf2[i] + cl * lm2 + cb * m2 - dt * (h12 * m1 + h22 * m2) + cSg * s2 + cSV * dv2;
+        const double o1 = lf1[i] + cl * lm1 + cb * m1 - dt * (h11 * m1 + h12 * m2) + cSg * s1 + cSV * dv1;
+        const double o2 = lf2[i] + cl * lm2 + cb * m2 - dt * (h12 * m1 + h22 * m2) + cSg * s2 + cSV * dv2;
+        of1[i] = o1;
+        of2[i] = o2;
         ov1[i] = m1;
         ov2[i] = m2;
+        if (NEXT) {
+            // the terms of k_adj_reduce for X_{k-1}, with lambda = (o, m)
+            auto w1 = [&](int dx, int dy, int dz) { return (double)n1[wr(dx, dy, dz)]; };
+            auto w2 = [&](int dx, int dy, int dz) { return (double)n2[wr(dx, dy, dz)]; };
+            const double b1 = (double)n1[i], b2 = (double)n2[i];
+            const double f1n = gn1 + b1, f2n = gn2 + b2;
+            const double t1 = lap_raw<ST, double>(w1, b1);
+            const double t2 = lap_raw<ST, double>(w2, b2);
+            const double mu1 = m1 + dt * o1, mu2 = m2 + dt * o2;
+            acc[0] += mu1 * t1 + mu2 * t2;
+            acc[1] += mu1 * f1n + mu2 * f2n;
+            acc[2] += mu1 * f1n * f2n * f2n + mu2 * f1n * f1n * f2n;
+            acc[3] += mu1 * ipw(f1n, beta - 1);
+            acc[4] += ipw(f1n, beta);
+            acc[5] += f1n * f1n * f2n * f2n;
+            acc[6] += grad_raw<ST>(w1, b1) + grad_raw<ST>(w2, b2);
+        }
     }
+    if (NEXT) bsum<7>(acc, part + (size_t)blockIdx.x * 7);
 }
 
 // Transpose of the desynchronisation f(1/2) = f(0) + dt/2 v(0) (in place on
@@ -356,30 +384,37 @@ void launch_adj_seed(int stencil, int dtype, const void *const s4[4], int N, con
 }
 
 template <typename T, int ST>
-static void adj_step_t(const void *d1, const void *d2, int N, int beta, const DevParams *P,
-                       const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
-                       double *part, int nblk, double *A, double *cf, int gridB, hipStream_t st)
+static void adj_step_t(const AdjStep &a, int N, int beta, const DevParams *P, double dt, double *part, int nblk,
+                       double *A, double *cf, int gridB, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_adj_reduce<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)d1, (const T *)d2, N,
-                       beta, tape, lin[0], lin[1], lin[2], lin[3], dt, part);
-    hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, tape, A, cf);
-    hipLaunchKernelGGL((k_adj_fields<T, ST>), dim3(gridB), dim3(256), 0, st, (const T *)d1, (const T *)d2, N,
-                       beta, tape, cf, lin[0], lin[1], lin[2], lin[3], lout[0], lout[1], lout[2], lout[3]);
+    if (!a.have_sums)
+        hipLaunchKernelGGL((k_adj_reduce<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)a.d1, (const T *)a.d2,
+                           N, beta, a.tape, a.lin[0], a.lin[1], a.lin[2], a.lin[3], dt, part);
+    hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, a.tape, A, cf);
+    if (a.next_d1)
+        hipLaunchKernelGGL((k_adj_fields<T, ST, true>), dim3(nblk), dim3(256), 0, st, (const T *)a.d1,
+                           (const T *)a.d2, N, beta, a.tape, cf, a.lin[0], a.lin[1], a.lin[2], a.lin[3], a.lout[0],
+                           a.lout[1], a.lout[2], a.lout[3], (const T *)a.next_d1, (const T *)a.next_d2,
+                           a.next_tape, part);
+    else
+        hipLaunchKernelGGL((k_adj_fields<T, ST, false>), dim3(gridB), dim3(256), 0, st, (const T *)a.d1,
+                           (const T *)a.d2, N, beta, a.tape, cf, a.lin[0], a.lin[1], a.lin[2], a.lin[3], a.lout[0],
+                           a.lout[1], a.lout[2], a.lout[3], (const T *)nullptr, (const T *)nullptr,
+                           (const DevScalars *)nullptr, (double *)nullptr);
 }
 
-void launch_adj_step(int stencil, int dtype, const void *d1, const void *d2, int N, int beta,
-                     const DevParams *P, const DevScalars *tape, double dt, double *const lin[4],
-                     double *const lout[4], double *part, int nblk, double *A, double *cf, hipStream_t st)
+void launch_adj_step(int stencil, int dtype, const AdjStep &a, int N, int beta, const DevParams *P, double dt,
+                     double *part, int nblk, double *A, double *cf, hipStream_t st)
 {
     const int64_t N3 = (int64_t)N * N * N;
     int64_t g = (N3 + 255) / 256;
     const int gridB = (int)(g > 65536 ? 65536 : g);
     if (stencil == 27) {
-        if (dtype == 0) adj_step_t<float, 27>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
-        else adj_step_t<double, 27>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
+        if (dtype == 0) adj_step_t<float, 27>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
+        else adj_step_t<double, 27>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
     } else {
-        if (dtype == 0) adj_step_t<float, 7>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
-        else adj_step_t<double, 7>(d1, d2, N, beta, P, tape, dt, lin, lout, part, nblk, A, cf, gridB, st);
+        if (dtype == 0) adj_step_t<float, 7>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
+        else adj_step_t<double, 7>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
     }
 }
 

@@ -782,10 +782,24 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
                 enqueue_step_io(c, in, out, c->stream, nullptr);
             }
         }
+        // reverse steps; inside a segment the fields pass of step j also
+        // forms the sums of step j - 1 (its stored state is at hand)
         for (int64_t j = m - 1; j >= 0; --j) {
             const char *src = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
-            launch_adj_step(stencil_of(&c->p), c->p.dtype, src, src + L.arr_bytes, c->p.N, c->p.beta, c->P, tape + j, c->p.dt,
-                            lam[li], lam[li ^ 1], part, kRedBlocks, A, cf, c->stream);
+            AdjStep a{};
+            a.d1 = src;
+            a.d2 = src + L.arr_bytes;
+            a.tape = tape + j;
+            a.lin = lam[li];
+            a.lout = lam[li ^ 1];
+            a.have_sums = j < m - 1;
+            if (j > 0) {
+                a.next_d1 = src - 4 * L.arr_bytes;
+                a.next_d2 = src - 3 * L.arr_bytes;
+                a.next_tape = tape + j - 1;
+            }
+            launch_adj_step(stencil_of(&c->p), c->p.dtype, a, c->p.N, c->p.beta, c->P, c->p.dt, part, kRedBlocks, A,
+                            cf, c->stream);
             li ^= 1;
         }
         HIPCHK(hipGetLastError());

@@ -122,8 +122,20 @@ constexpr int kNAdjPart = 7;
 void launch_adj_seed(int stencil, int dtype, const void *const s4[4], int N, const DevParams *P, const DevScalars *S,
                      const double *w, double *const lam[4], double *part, int nblk, double *A,
                      hipStream_t st);
-void launch_adj_step(int stencil, int dtype, const void *d1, const void *d2, int N, int beta, const DevParams *P,
-                     const DevScalars *tape, double dt, double *const lin[4], double *const lout[4],
+// One reverse step: stored fields d1, d2 and scalars tape of X_k, cotangents
+// lin (of X_{k+1}) -> lout (of X_k).  have_sums: part already holds the
+// step's sums (formed by the previous step's fields pass).  next_*: when set,
+// the fields pass also forms the sums of the next reverse step (X_{k-1}).
+struct AdjStep {
+    const void *d1, *d2;
+    const DevScalars *tape;
+    double *const *lin;
+    double *const *lout;
+    bool have_sums;
+    const void *next_d1, *next_d2;
+    const DevScalars *next_tape;
+};
+void launch_adj_step(int stencil, int dtype, const AdjStep &a, int N, int beta, const DevParams *P, double dt,
                      double *part, int nblk, double *A, double *cf, hipStream_t st);
 void launch_adj_desync(int N, double dt, double *const lam[4], double *A, hipStream_t st);
 void launch_set_pending(double *part, int nblk, const double *totals, hipStream_t st);
