@@ -7,12 +7,15 @@
 //   pass A  (k_adj_reduce): volume sums of the incoming cotangent against the
 //           stored fields (the global a'' coupling) and of the fields themselves;
 //   scalar  (k_adj_scalar): the chain through a'', the time-centred a' update,
-//           F_a and the a-powers of V_pr, in FP64, one thread;
+//           F_a and the a-powers of V_pr, in FP64, one thread (the powers on
+//           parallel lanes);
 //   pass B  (k_adj_fields): the field cotangents: the Laplacian (7 or 27
 //           points) of mu = lambda_v' + dt lambda_f' (both stencils are
 //           symmetric), the local 2x2 Hessian of V_pr, and the rank-one terms
 //           from Sg and SV (the derivative of the gradient energy is -2 Lap f,
-//           since it is the Dirichlet form of the same Laplacian).
+//           since it is the Dirichlet form of the same Laplacian); inside a
+//           segment of stored states it also forms pass A of the next
+//           reverse step.
 // Cotangent arrays are FP64 whatever the state precision; stored states are
 // deviations from the FP64 background and are turned back into full fields
 // f = f_bar + d in FP64 on the fly.
@@ -274,11 +277,37 @@ __global__ void __launch_bounds__(256) k_adj_scalar(const double *part, int nblk
     cf[6] = dt;
 }
 
-// Pass B: field cotangents of X_k from those of X_{k+1} (in -> out).
-// NEXT: also pass A of the next reverse step (X_{k-1}: stored fields n1, n2,
-// scalars tape_n) over the cotangents just written, into part; launched on
-// the grid of k_adj_reduce, so every site meets the same thread and the
-// sums are bitwise those of a separate k_adj_reduce.
+// Pass B: field cotangents of X_k from those of X_{k+1} (in -> out), with
+// NEXT also pass A of the next reverse step (X_{k-1}: stored fields n1, n2,
+// scalars tape_n) over the cotangents just written, into part.
+//
+// It needs, per site, mu = lambda_v' + dt lambda_f' and the stored d (and n)
+// at every stencil neighbour in planes z-1, z, z+1.  A block owns a 64 x 4
+// column tile and marches z over a chunk: the three planes sit in LDS with a
+// one-cell ring (four buffers, so one barrier per plane), and plane z+2 is
+// loaded into registers while plane z is evaluated.  The grid walks a static
+// list of (tile, chunk) items.  The per-site arithmetic is that of the
+// generic one-site-per-thread formulation.
+constexpr int kAX = 64, kAY = 4;
+constexpr int kALW = kAX + 2, kALH = kAY + 2, kAPL = kALW * kALH;  // plane with its ring
+constexpr int kARing = 2 * kALW + 2 * kAY;
+
+__device__ inline void adj_ring_cell(int c, int &lx, int &ly)
+{
+    if (c < kALW) { lx = c - 1; ly = -1; }
+    else if (c < 2 * kALW) { lx = c - kALW - 1; ly = kAY; }
+    else if (c < 2 * kALW + kAY) { lx = -1; ly = c - 2 * kALW; }
+    else { lx = kAX; ly = c - 2 * kALW - kAY; }
+}
+
+// LDS bytes of k_adj_fields: four planes of mu1, mu2 (FP64) and the stored
+// fields d1, d2 (and n1, n2 with NEXT) in their own type.
+template <typename T, bool NEXT>
+constexpr size_t adj_fields_lds()
+{
+    return (size_t)4 * kAPL * (2 * sizeof(double) + (NEXT ? 4 : 2) * sizeof(T));
+}
+
 template <typename T, int ST, bool NEXT>
 __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, const T *__restrict__ d2,
                                                     int N, int beta, const DevScalars *__restrict__ tape,
@@ -287,61 +316,131 @@ __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, co
                                                     const double *__restrict__ lv1, const double *__restrict__ lv2,
                                                     double *of1, double *of2, double *ov1, double *ov2,
                                                     const T *__restrict__ n1, const T *__restrict__ n2,
-                                                    const DevScalars *__restrict__ tape_n, double *part)
+                                                    const DevScalars *__restrict__ tape_n, double *part,
+                                                    int zchunk, int ntx, int nty, int nitems)
 {
-    const int64_t N3 = (int64_t)N * N * N;
+    extern __shared__ double lds[];
+    // buffer b: mu1, mu2 (doubles) at lds + b * 2 * kAPL; fields in type T after all mu planes
+    double *smu = lds;
+    T *sfl = (T *)(lds + 4 * 2 * kAPL);
+    constexpr int NF = NEXT ? 4 : 2;  // d1, d2 [, n1, n2]
+    auto MU = [&](int b, int q) { return smu + (b * 2 + q) * kAPL; };
+    auto FL = [&](int b, int q) { return sfl + (b * NF + q) * kAPL; };
+
+    const int64_t NN = (int64_t)N * N;
     const double g1 = tape->bg_f[0], g2 = tape->bg_f[1];
     const double cl = cf[0], cb = cf[1], c1a = cf[2], Ga = cf[3], cSg = cf[4], cSV = cf[5], dt = cf[6];
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const double gn1 = NEXT ? tape_n->bg_f[0] : 0.0, gn2 = NEXT ? tape_n->bg_f[1] : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N3;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const Wrap wr(i, N);
-        auto mu1 = [&](int dx, int dy, int dz) {
-            const int64_t j = wr(dx, dy, dz);
-            return lv1[j] + dt * lf1[j];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+
+    const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+    const int slot = (ly + 1) * kALW + lx + 1;
+    const bool hasr = t < kARing;
+    int rx = 0, ry = 0;
+    if (hasr) adj_ring_cell(t, rx, ry);
+    const int rslot = (ry + 1) * kALW + rx + 1;
+    auto wrap = [N](int v) { return ((v % N) + N) % N; };
+    // plane z in [-1, N]: one wrap suffices
+    auto zoff = [&](int z) { return (int64_t)(z < 0 ? z + N : (z >= N ? z - N : z)) * NN; };
+
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tx = item % ntx, rest = item / ntx, ty = rest % nty, tz = rest / nty;
+        const int x0 = tx * kAX, y0 = ty * kAY, z0 = tz * zchunk;
+        const int z1 = min(z0 + zchunk, N);
+        const bool act = (x0 + lx < N) && (y0 + ly < N);
+        const int off = wrap(y0 + ly) * N + wrap(x0 + lx);
+        const int roff = wrap(y0 + ry) * N + wrap(x0 + rx);
+
+        // the plane in flight, site and ring cell
+        double pf1, pf2, pv1, pv2, hf1 = 0, hf2 = 0, hv1 = 0, hv2 = 0;
+        T pd1, pd2, hd1 = 0, hd2 = 0, pn1 = 0, pn2 = 0, hn1 = 0, hn2 = 0;
+        auto load = [&](int z) {
+            const int64_t o = zoff(z) + off;
+            pf1 = lf1[o]; pf2 = lf2[o]; pv1 = lv1[o]; pv2 = lv2[o];
+            pd1 = d1[o]; pd2 = d2[o];
+            if (NEXT) { pn1 = n1[o]; pn2 = n2[o]; }
+            if (hasr) {
+                const int64_t h = zoff(z) + roff;
+                hf1 = lf1[h]; hf2 = lf2[h]; hv1 = lv1[h]; hv2 = lv2[h];
+                hd1 = d1[h]; hd2 = d2[h];
+                if (NEXT) { hn1 = n1[h]; hn2 = n2[h]; }
+            }
         };
-        auto mu2 = [&](int dx, int dy, int dz) {
-            const int64_t j = wr(dx, dy, dz);
-            return lv2[j] + dt * lf2[j];
+        auto stage = [&](int b) {
+            MU(b, 0)[slot] = pv1 + dt * pf1;
+            MU(b, 1)[slot] = pv2 + dt * pf2;
+            FL(b, 0)[slot] = pd1;
+            FL(b, 1)[slot] = pd2;
+            if (NEXT) { FL(b, 2)[slot] = pn1; FL(b, 3)[slot] = pn2; }
+            if (hasr) {
+                MU(b, 0)[rslot] = hv1 + dt * hf1;
+                MU(b, 1)[rslot] = hv2 + dt * hf2;
+                FL(b, 0)[rslot] = hd1;
+                FL(b, 1)[rslot] = hd2;
+                if (NEXT) { FL(b, 2)[rslot] = hn1; FL(b, 3)[rslot] = hn2; }
+            }
         };
-        auto v1 = [&](int dx, int dy, int dz) { return (double)d1[wr(dx, dy, dz)]; };
-        auto v2 = [&](int dx, int dy, int dz) { return (double)d2[wr(dx, dy, dz)]; };
-        const double m1 = lv1[i] + dt * lf1[i], m2 = lv2[i] + dt * lf2[i];
-        const double lm1 = lap_raw<ST, double>(mu1, m1);
-        const double lm2 = lap_raw<ST, double>(mu2, m2);
-        const double a1 = (double)d1[i], a2 = (double)d2[i];
-        const double s1 = lap_raw<ST, double>(v1, a1);
-        const double s2 = lap_raw<ST, double>(v2, a2);
-        const double f1 = g1 + a1, f2 = g2 + a2;
-        const double h11 = c1a * (double)(beta - 1) * ipw(f1, beta - 2) + Ga * f2 * f2;
-        const double h12 = 2.0 * Ga * f1 * f2;
-        const double h22 = Ga * f1 * f1;
-        const double dv1 = c1a * ipw(f1, beta - 1) + Ga * f1 * f2 * f2;
-        const double dv2 = Ga * f1 * f1 * f2;
-        const double o1 = lf1[i] + cl * lm1 + cb * m1 - dt * (h11 * m1 + h12 * m2) + cSg * s1 + cSV * dv1;
-        const double o2 = lf2[i] + cl * lm2 + cb * m2 - dt * (h12 * m1 + h22 * m2) + cSg * s2 + cSV * dv2;
-        of1[i] = o1;
-        of2[i] = o2;
-        ov1[i] = m1;
-        ov2[i] = m2;
-        if (NEXT) {
-            // the terms of k_adj_reduce for X_{k-1}, with lambda = (o, m)
-            auto w1 = [&](int dx, int dy, int dz) { return (double)n1[wr(dx, dy, dz)]; };
-            auto w2 = [&](int dx, int dy, int dz) { return (double)n2[wr(dx, dy, dz)]; };
-            const double b1 = (double)n1[i], b2 = (double)n2[i];
-            const double f1n = gn1 + b1, f2n = gn2 + b2;
-            const double t1 = lap_raw<ST, double>(w1, b1);
-            const double t2 = lap_raw<ST, double>(w2, b2);
-            const double mu1 = m1 + dt * o1, mu2 = m2 + dt * o2;
-            acc[0] += mu1 * t1 + mu2 * t2;
-            acc[1] += mu1 * f1n + mu2 * f2n;
-            acc[2] += mu1 * f1n * f2n * f2n + mu2 * f1n * f1n * f2n;
-            acc[3] += mu1 * ipw(f1n, beta - 1);
-            acc[4] += ipw(f1n, beta);
-            acc[5] += f1n * f1n * f2n * f2n;
-            acc[6] += grad_raw<ST>(w1, b1) + grad_raw<ST>(w2, b2);
+        // plane p lives in buffer (p - z0 + 1) & 3; own lambda_f of planes z, z+1
+        double lc1, lc2, ln1, ln2;
+        load(z0 - 1);
+        stage(0);
+        load(z0);
+        stage(1);
+        lc1 = pf1; lc2 = pf2;
+        load(z0 + 1);
+        for (int z = z0; z < z1; ++z) {
+            const int bp = (z - z0) & 3, bc = (z - z0 + 1) & 3, bn = (z - z0 + 2) & 3;
+            // plane z+1 into the buffer last read for plane z-3
+            stage(bn);
+            ln1 = pf1; ln2 = pf2;
+            if (z + 2 <= z1) load(z + 2);
+            __syncthreads();
+            if (act) {
+                auto pick = [&](int dz) { return dz < 0 ? bp : (dz > 0 ? bn : bc); };
+                auto mu1 = [&](int dx, int dy, int dz) { return MU(pick(dz), 0)[slot + dy * kALW + dx]; };
+                auto mu2 = [&](int dx, int dy, int dz) { return MU(pick(dz), 1)[slot + dy * kALW + dx]; };
+                auto v1 = [&](int dx, int dy, int dz) { return (double)FL(pick(dz), 0)[slot + dy * kALW + dx]; };
+                auto v2 = [&](int dx, int dy, int dz) { return (double)FL(pick(dz), 1)[slot + dy * kALW + dx]; };
+                const double m1 = MU(bc, 0)[slot], m2 = MU(bc, 1)[slot];
+                const double lm1 = lap_raw<ST, double>(mu1, m1);
+                const double lm2 = lap_raw<ST, double>(mu2, m2);
+                const double a1 = (double)FL(bc, 0)[slot], a2 = (double)FL(bc, 1)[slot];
+                const double s1 = lap_raw<ST, double>(v1, a1);
+                const double s2 = lap_raw<ST, double>(v2, a2);
+                const double f1 = g1 + a1, f2 = g2 + a2;
+                const double h11 = c1a * (double)(beta - 1) * ipw(f1, beta - 2) + Ga * f2 * f2;
+                const double h12 = 2.0 * Ga * f1 * f2;
+                const double h22 = Ga * f1 * f1;
+                const double dv1 = c1a * ipw(f1, beta - 1) + Ga * f1 * f2 * f2;
+                const double dv2 = Ga * f1 * f1 * f2;
+                const double o1 = lc1 + cl * lm1 + cb * m1 - dt * (h11 * m1 + h12 * m2) + cSg * s1 + cSV * dv1;
+                const double o2 = lc2 + cl * lm2 + cb * m2 - dt * (h12 * m1 + h22 * m2) + cSg * s2 + cSV * dv2;
+                const int64_t i = (int64_t)z * NN + off;
+                of1[i] = o1;
+                of2[i] = o2;
+                ov1[i] = m1;
+                ov2[i] = m2;
+                if (NEXT) {
+                    // the terms of k_adj_reduce for X_{k-1}, with lambda = (o, m)
+                    auto w1 = [&](int dx, int dy, int dz) { return (double)FL(pick(dz), 2)[slot + dy * kALW + dx]; };
+                    auto w2 = [&](int dx, int dy, int dz) { return (double)FL(pick(dz), 3)[slot + dy * kALW + dx]; };
+                    const double b1 = (double)FL(bc, 2)[slot], b2 = (double)FL(bc, 3)[slot];
+                    const double f1n = gn1 + b1, f2n = gn2 + b2;
+                    const double t1 = lap_raw<ST, double>(w1, b1);
+                    const double t2 = lap_raw<ST, double>(w2, b2);
+                    const double nu1 = m1 + dt * o1, nu2 = m2 + dt * o2;
+                    acc[0] += nu1 * t1 + nu2 * t2;
+                    acc[1] += nu1 * f1n + nu2 * f2n;
+                    acc[2] += nu1 * f1n * f2n * f2n + nu2 * f1n * f1n * f2n;
+                    acc[3] += nu1 * ipw(f1n, beta - 1);
+                    acc[4] += ipw(f1n, beta);
+                    acc[5] += f1n * f1n * f2n * f2n;
+                    acc[6] += grad_raw<ST>(w1, b1) + grad_raw<ST>(w2, b2);
+                }
+            }
+            lc1 = ln1; lc2 = ln2;
         }
+        __syncthreads();  // the next item restages buffers 0 and 1
     }
     if (NEXT) bsum<7>(acc, part + (size_t)blockIdx.x * 7);
 }
@@ -383,38 +482,74 @@ void launch_adj_seed(int stencil, int dtype, const void *const s4[4], int N, con
     hipLaunchKernelGGL(k_adj_seed_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, S, w, A);
 }
 
+// Items and grid of the marching field pass: z-chunks chosen so that the
+// (tile, chunk) items fill about `rows` blocks; grid = min(items, rows), which
+// is also the number of partial rows the fused sums fill.
+struct AdjGrid {
+    int ntx, nty, zchunk, items, grid;
+};
+
+static AdjGrid adj_grid(int N, int rows)
+{
+    AdjGrid g;
+    g.ntx = (N + kAX - 1) / kAX;
+    g.nty = (N + kAY - 1) / kAY;
+    int nz = rows / (g.ntx * g.nty);
+    nz = nz < 1 ? 1 : (nz > N ? N : nz);
+    g.zchunk = (N + nz - 1) / nz;
+    nz = (N + g.zchunk - 1) / g.zchunk;
+    g.items = g.ntx * g.nty * nz;
+    g.grid = g.items < rows ? g.items : rows;
+    return g;
+}
+
+// Target number of field-pass items: two blocks per CU of the 256-CU part,
+// so that chunks are long next to the two planes each chunk stages first
+// (128^3: 16-plane chunks; 2048 items of 4 planes took 20% longer).
+constexpr int kAdjItems = 512;
+
 template <typename T, int ST>
 static void adj_step_t(const AdjStep &a, int N, int beta, const DevParams *P, double dt, double *part, int nblk,
-                       double *A, double *cf, int gridB, hipStream_t st)
+                       double *A, double *cf, hipStream_t st)
 {
-    if (!a.have_sums)
+    const AdjGrid g = adj_grid(N, nblk < kAdjItems ? nblk : kAdjItems);
+    // the step's sums: from the previous field pass (g.grid rows) or from a
+    // reduction pass of their own (nblk rows)
+    int rows = g.grid;
+    if (!a.have_sums) {
         hipLaunchKernelGGL((k_adj_reduce<T, ST>), dim3(nblk), dim3(256), 0, st, (const T *)a.d1, (const T *)a.d2,
                            N, beta, a.tape, a.lin[0], a.lin[1], a.lin[2], a.lin[3], dt, part);
-    hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, nblk, P, a.tape, A, cf);
-    if (a.next_d1)
-        hipLaunchKernelGGL((k_adj_fields<T, ST, true>), dim3(nblk), dim3(256), 0, st, (const T *)a.d1,
+        rows = nblk;
+    }
+    hipLaunchKernelGGL(k_adj_scalar, dim3(1), dim3(256), 0, st, part, rows, P, a.tape, A, cf);
+    if (a.next_d1) {
+        constexpr size_t lds = adj_fields_lds<T, true>();
+        (void)hipFuncSetAttribute((const void *)k_adj_fields<T, ST, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_adj_fields<T, ST, true>), dim3(g.grid), dim3(256), lds, st, (const T *)a.d1,
                            (const T *)a.d2, N, beta, a.tape, cf, a.lin[0], a.lin[1], a.lin[2], a.lin[3], a.lout[0],
                            a.lout[1], a.lout[2], a.lout[3], (const T *)a.next_d1, (const T *)a.next_d2,
-                           a.next_tape, part);
-    else
-        hipLaunchKernelGGL((k_adj_fields<T, ST, false>), dim3(gridB), dim3(256), 0, st, (const T *)a.d1,
+                           a.next_tape, part, g.zchunk, g.ntx, g.nty, g.items);
+    } else {
+        constexpr size_t lds = adj_fields_lds<T, false>();
+        (void)hipFuncSetAttribute((const void *)k_adj_fields<T, ST, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_adj_fields<T, ST, false>), dim3(g.grid), dim3(256), lds, st, (const T *)a.d1,
                            (const T *)a.d2, N, beta, a.tape, cf, a.lin[0], a.lin[1], a.lin[2], a.lin[3], a.lout[0],
                            a.lout[1], a.lout[2], a.lout[3], (const T *)nullptr, (const T *)nullptr,
-                           (const DevScalars *)nullptr, (double *)nullptr);
+                           (const DevScalars *)nullptr, (double *)nullptr, g.zchunk, g.ntx, g.nty, g.items);
+    }
 }
 
 void launch_adj_step(int stencil, int dtype, const AdjStep &a, int N, int beta, const DevParams *P, double dt,
                      double *part, int nblk, double *A, double *cf, hipStream_t st)
 {
-    const int64_t N3 = (int64_t)N * N * N;
-    int64_t g = (N3 + 255) / 256;
-    const int gridB = (int)(g > 65536 ? 65536 : g);
     if (stencil == 27) {
-        if (dtype == 0) adj_step_t<float, 27>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
-        else adj_step_t<double, 27>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
+        if (dtype == 0) adj_step_t<float, 27>(a, N, beta, P, dt, part, nblk, A, cf, st);
+        else adj_step_t<double, 27>(a, N, beta, P, dt, part, nblk, A, cf, st);
     } else {
-        if (dtype == 0) adj_step_t<float, 7>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
-        else adj_step_t<double, 7>(a, N, beta, P, dt, part, nblk, A, cf, gridB, st);
+        if (dtype == 0) adj_step_t<float, 7>(a, N, beta, P, dt, part, nblk, A, cf, st);
+        else adj_step_t<double, 7>(a, N, beta, P, dt, part, nblk, A, cf, st);
     }
 }
 

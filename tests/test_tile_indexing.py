@@ -227,3 +227,99 @@ def test_diag_march_items_beyond_grid(N, rows):
 
 def test_sweep27_staging_and_bond_ownership(case):
     check_sweep27(*case)
+
+
+# ---- k_adj_fields: tile 64 x 4, four LDS planes of (64 + 2) x (4 + 2), full ring
+AX, AY = 64, 4
+ALW, ALH = AX + 2, AY + 2
+APL = ALW * ALH
+ARING = 2 * ALW + 2 * AY
+
+
+def adj_ring_cell(c):
+    if c < ALW:
+        return c - 1, -1
+    if c < 2 * ALW:
+        return c - ALW - 1, AY
+    if c < 2 * ALW + AY:
+        return -1, c - 2 * ALW
+    return AX, c - 2 * ALW - AY
+
+
+def adj_grid(N, rows):
+    ntx = (N + AX - 1) // AX
+    nty = (N + AY - 1) // AY
+    nz = max(1, min(N, rows // (ntx * nty)))
+    zc = (N + nz - 1) // nz
+    nz = (N + zc - 1) // zc
+    items = ntx * nty * nz
+    return ntx, nty, zc, items, min(items, rows)
+
+
+def check_adj(N, rows=512):
+    """Every LDS index in range, every gathered value of planes z-1, z, z+1
+    the periodic neighbour, each site evaluated once, and the buffer a plane
+    is staged into last read two iterations earlier (one barrier apart)."""
+    rng = np.random.default_rng(N)
+    f = rng.standard_normal((N, N, N))
+    ntx, nty, zc, items, grid = adj_grid(N, rows)
+    seen = np.zeros((N, N, N), int)
+    t = np.arange(256)
+    lx, ly = t & 63, t >> 6
+    slot = (ly + 1) * ALW + lx + 1
+    hasr = t < ARING
+    rc = [adj_ring_cell(int(c)) if c < ARING else (0, 0) for c in t]
+    rx = np.array([a for a, _ in rc])
+    ry = np.array([b for _, b in rc])
+    rslot = (ry + 1) * ALW + rx + 1
+    assert slot.max() < APL and rslot.min() >= 0 and rslot.max() < APL
+    assert not set(slot) & set(rslot[hasr])
+    for blk in range(grid):
+        for item in range(blk, items, grid):
+            tx = item % ntx
+            rest = item // ntx
+            ty, tz = rest % nty, rest // nty
+            x0, y0, z0 = tx * AX, ty * AY, tz * zc
+            z1 = min(z0 + zc, N)
+            act = (x0 + lx < N) & (y0 + ly < N)
+            xi, yi = (x0 + lx) % N, (y0 + ly) % N
+            xr, yr = (x0 + rx) % N, (y0 + ry) % N
+            buf, last_read = {}, {}
+
+            def stage(b, z, it):
+                assert -1 <= z <= N
+                # the buffer's previous plane was last read at least two
+                # iterations ago (a barrier lies between)
+                assert last_read.get(b, -10) <= it - 2, (b, last_read.get(b), it)
+                p = np.full(APL, np.nan)
+                p[slot] = f[z % N, yi, xi]
+                p[rslot[hasr]] = f[z % N, yr[hasr], xr[hasr]]
+                buf[b] = (z, p)
+
+            stage(0, z0 - 1, -5)
+            stage(1, z0, -5)
+            for z in range(z0, z1):
+                it = z - z0
+                bp, bc, bn = (z - z0) & 3, (z - z0 + 1) & 3, (z - z0 + 2) & 3
+                stage(bn, z + 1, it)
+                for b in (bp, bc, bn):
+                    last_read[b] = it
+                assert buf[bp][0] == z - 1 and buf[bc][0] == z and buf[bn][0] == z + 1
+                a = act
+                for dz, b in ((-1, bp), (0, bc), (1, bn)):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            idx = slot[a] + dy * ALW + dx
+                            assert idx.min() >= 0 and idx.max() < APL
+                            got = buf[b][1][idx]
+                            want = f[(z + dz) % N, (y0 + ly[a] + dy) % N, (x0 + lx[a] + dx) % N]
+                            assert np.array_equal(got, want), (N, item, z, dx, dy, dz)
+                seen[z, (y0 + ly[a]) % N, (x0 + lx[a]) % N] += 1
+    assert (seen == 1).all()
+    return grid
+
+
+@pytest.mark.parametrize("N,rows", [(4, 512), (5, 512), (9, 512), (33, 512), (67, 512), (128, 512), (20, 7), (12, 1)])
+def test_adj_fields_march_indexing(N, rows):
+    grid = check_adj(N, rows)
+    assert grid <= rows
