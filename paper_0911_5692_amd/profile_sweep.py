@@ -9,6 +9,8 @@ Two steps, each its own process:
   summarize  reads the two counter CSVs (and optionally a --kernel-trace
              --stats CSV), scales each counter by what it reads for the copy,
              and writes profiles/sweep_traffic_<workload>.json and .md.
+  kernels    writes the per-kernel table of any --kernel-trace --stats run
+             (every kernel a benchmark run launched) as markdown.
 
 FETCH_SIZE and WRITE_SIZE are in KiB per dispatch.  The calibration factor of
 a counter is (bytes the copy moves) / (what the counter reads for the copy).
@@ -166,6 +168,21 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
     return res
 
 
+def kernel_table(trace_dir: str, out_path: str, commands: list[str], title: str) -> None:
+    """Markdown table of every kernel of a rocprofv3 --kernel-trace --stats run
+    (calls, average and total duration), with the commands that made it."""
+    stats = _rows(_find(trace_dir, "kernel_stats.csv"))
+    with open(out_path, "w") as fh:
+        fh.write(f"# {title}\n\nCommands (from the repository root on the GPU host):\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write("\n| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|\n")
+        for r in stats:
+            name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0][:100]
+            fh.write(f"| {name} | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |\n")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -179,9 +196,16 @@ def main() -> int:
     s.add_argument("--trace-dir")
     s.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
     s.add_argument("--command", action="append", default=[])
+    k = sub.add_parser("kernels")
+    k.add_argument("--trace-dir", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--title", default="Kernel trace")
+    k.add_argument("--command", action="append", default=[])
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.workload, a.steps)
+    elif a.cmd == "kernels":
+        kernel_table(a.trace_dir, a.out, a.command, a.title)
     else:
         res = summarize(a.workload, a.fetch_dir, a.write_dir, a.trace_dir, a.out_dir, a.command)
         print(json.dumps(res))
