@@ -83,7 +83,7 @@ Shape shape_of(const lf_params *p)
         sh.tile_y = p->tile_y;
         sh.tile_x = p->tile_x ? p->tile_x : 64;
     } else if (N >= 256) {
-        sh.tile_x = stencil_of(p) == 27 ? 64 : 128;
+        sh.tile_x = 128;
         sh.tile_y = 8;
     } else {
         sh.tile_x = 64;
@@ -99,13 +99,14 @@ Shape shape_of(const lf_params *p)
         sh.zchunk = p->zchunk < N ? p->zchunk : N;
     } else {
         // The whole grid resident at once (tiles march in lockstep and find
-        // their neighbours' halo lines in L2).  The FP32 7-point sweep with
-        // 128-wide tiles does best with two blocks per CU: a smaller L2
-        // working set per XCD and long chunks (at 512^3: 256 planes, fetch
-        // 1.03x the algorithmic reads against 1.16x with three blocks per CU
-        // and 64 planes; 256^3: 32 planes).  The other sweeps fill the CUs
-        // and keep chunks of at most 64 planes.
-        const bool two_per_cu = stencil_of(p) == 7 && p->dtype == LF_F32 && sh.tile_x == 128;
+        // their neighbours' halo lines in L2).  The FP32 sweeps with 128-wide
+        // tiles do best with two blocks per CU: a smaller L2 working set per
+        // XCD and long chunks (7 points at 512^3: 256 planes, fetch 1.03x the
+        // algorithmic reads against 1.16x with three blocks per CU and 64
+        // planes; 256^3: 32 planes; 27 points: 6% faster at 512^3 and 11% at
+        // 256^3 than 64-wide tiles filling the CUs).  The other sweeps fill
+        // the CUs and keep chunks of at most 64 planes.
+        const bool two_per_cu = p->dtype == LF_F32 && sh.tile_x == 128;
         const int per_slab = ((N + sh.tile_x - 1) / sh.tile_x) * ((N + sh.tile_y - 1) / sh.tile_y);
         const int res = resident_blocks(p, sh.tile_x, sh.tile_y);
         const int target = two_per_cu && 2 * cu_count() < res ? 2 * cu_count() : res;

@@ -98,13 +98,12 @@ def ensemble_members():
 WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5, CFG3_S27, PAPER_256_S27)}
 
 # Sweep launch shapes used by the benchmark, measured on an MI355X (gfx950)
-# with lf_autotune and sweeps of tiles and z-chunks; for the 27-point sweep
-# z-chunks of 64 to 171 planes time within the spread between machines (2-5%).
-# Re-run the autotuner (bench.py --autotune) on other parts.
+# with lf_autotune and sweeps of tiles and z-chunks.  Re-run the autotuner
+# (bench.py --autotune) on other parts.
 BENCH_SHAPES = {
     CFG3.name: dict(tile_x=128, tile_y=8, zchunk=256),
-    CFG3_S27.name: dict(tile_x=64, tile_y=8, zchunk=64),
-    PAPER_256_S27.name: dict(tile_x=64, tile_y=8, zchunk=43),
+    CFG3_S27.name: dict(tile_x=128, tile_y=8, zchunk=256),
+    PAPER_256_S27.name: dict(tile_x=128, tile_y=8, zchunk=32),
 }
 
 
