@@ -92,11 +92,12 @@ typedef struct lf_params {
     int32_t tile_y;   /* sweep tile rows: 0 = automatic, 1 = plain one-site-per-thread
                          sweep with a separate reduction, 4, 8 or 16 = LDS z-march */
     int32_t zchunk;   /* planes per z-chunk of the LDS sweep, 0 = automatic (a grid that
-                         is resident at once: two blocks per CU for the FP32 7-point
-                         sweep with 128-wide tiles, else as many as fit, with chunks
-                         of at most 64 planes) */
-    int32_t tile_x;   /* sweep tile columns: 0 = automatic, 64 or 128 (128 with
-                         tile_y 4 or 8 only) */
+                         is resident at once: two blocks per CU for FP32 sweeps with
+                         128-wide tiles, else as many as fit, with chunks of at most
+                         64 planes) */
+    int32_t tile_x;   /* sweep tile columns: 0 = automatic (128 x 8 from N = 256 up,
+                         64 x 8 or 64 x 4 below), 64 or 128 (128 with tile_y 4 or 8
+                         only) */
     int32_t stencil;  /* Laplacian: 0 or 7 = 7-point, 27 = 27-point (see above) */
 } lf_params;
 
