@@ -83,6 +83,14 @@ def test_full_size_512_periodic_tiles():
     _check(w, 400, "f32", reps=8, **W.BENCH_SHAPES[W.CFG3_S27.name])
 
 
+def test_paper_configuration_256_periodic_tiles():
+    """256^3 FP32 in the launch shape the benchmark times the paper's own
+    configuration with (64^3-periodic initial state): every periodic copy
+    bitwise equal, and equal to the oracle's 64^3 evolution, after 600 steps."""
+    w = W.PAPER_256_S27.resized(64)
+    _check(w, 600, "f32", reps=4, **W.BENCH_SHAPES[W.PAPER_256_S27.name])
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-5)])
 def test_free_wave_exact_discrete_solution(dtype, tol):
     """kappa^2 = 0, G = 0, V = c1 f^2/2: cos(k.x) evolves as cos(k Omega dt)
