@@ -226,6 +226,42 @@ int lf_last_step_ms(lf_ctx *ctx, double *ms);
 int lf_stream_copy(const float *a0, const float *a1, const float *a2, const float *a3, float *b0, float *b1,
                    float *b2, float *b3, int64_t n, void *stream);
 
+/* ---- one GPU's share of a lattice split into z-slabs ------------------- */
+
+/* The fused kick-drift sweep of one step (eqs. evo, with the Laplacian and
+ * the in-sweep sums of Sec. II.C) on a slab of nz consecutive z-planes of the
+ * context's N^3 lattice, as one GPU runs it when the lattice is split along
+ * z: the periodic wrap in z is replaced by halo planes received from the two
+ * neighbouring slabs.  x and y stay periodic over N.
+ *
+ * in[4]   d1, d2, e1, e2 of the slab (context dtype, deviations from the
+ *         background as the context stores them): nz planes of N*N, x fastest.
+ * lo[4]   halo below the slab: d1, d2: planes -2 and -1 (2 planes each, -2
+ *         first); e1, e2: plane -1 (1 plane each).
+ * hi[2]   halo above the slab: d1, d2: plane nz (1 plane each).
+ * out[4]  the new d1, d2, e1, e2 of the slab (nz planes each).
+ * partials  device array of partial_rows x 4 doubles; the sweep writes
+ *         lf_slab_rows(ctx, nz, zchunk) rows: per block, the sums over its
+ *         sites of the two gradient energies, f1^beta and f1^2 f2^2 of the new
+ *         fields (the bonds and sites the slab owns: planes 0 .. nz-1 and the
+ *         z-bonds between plane -1 and plane 0).  The rows of all slabs
+ *         together hold the same bonds and sites as the periodic step's rows.
+ * zchunk  planes per block (0: automatic, as for the context's own sweep).
+ *
+ * The coefficients are those of the context's last step (the scale-factor
+ * update that opened it), so with the state that step started from, split
+ * into slabs, the outputs equal that step's outputs bitwise.  The context's
+ * launch shape must be an LDS one (tile_y 4, 8 or 16).  Pointers are device
+ * arrays aligned to the element size, caller-owned; outputs may not overlap
+ * any other array.  Asynchronous on the context's stream.  Errors: LF_EINVAL
+ * (bad arguments, nz outside [1, N], partials too small), LF_ESTATE (no step
+ * since lf_init / lf_set_state), LF_EHIP.  Exchanging halos and summing the
+ * partial rows across slabs (then the scale-factor update from the global
+ * sums) is the multi-GPU driver's part and is not in this library. */
+int lf_slab_rows(const lf_ctx *ctx, int nz, int zchunk, int64_t *rows);
+int lf_slab_sweep(lf_ctx *ctx, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                  const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows);
+
 /* ---- autotuner ---------------------------------------------------------- */
 
 /* Workspace for lf_autotune with these parameters (largest candidate). */

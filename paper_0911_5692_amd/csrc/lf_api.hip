@@ -44,16 +44,14 @@ struct Shape {
     int tile_x, tile_y, zchunk, rows;  // rows: partial-sum rows the step reduction writes
 };
 
-// Automatic launch shape.  Tiles of 128 x 8 for large lattices (64 x 8 for
-// the 27-point stencil, whose sweep is limited by its arithmetic and prefers
-// more blocks), narrower ones below.  The z-chunk is chosen so that the whole
-// grid is resident at once (resident blocks = blocks per CU from the
-// occupancy calculator x CU count): all tiles then march their chunks in
-// lockstep and the halo rows a tile shares with its neighbours are still in
-// L2 when they are needed.  It is capped at 64 planes, which the autotuner
-// prefers on gfx950 for the large lattices.  The resident count is only
-// queried on a machine with a GPU; elsewhere (and for the workspace size) 3
-// blocks on 256 CUs is assumed, which only changes the partial-sum row count.
+// Automatic launch shape.  Tiles of 128 x 8 from N = 256 (both stencils),
+// narrower ones below.  The z-chunk is chosen so that the whole grid is
+// resident at once (resident blocks = blocks per CU from the occupancy
+// calculator x CU count): all tiles then march their chunks in lockstep and
+// the halo rows a tile shares with its neighbours are still in L2 when they
+// are needed (see auto_zchunk).  The resident count is only queried on a
+// machine with a GPU; elsewhere (and for the workspace size) 3 blocks on 256
+// CUs is assumed, which only changes the partial-sum row count.
 // 7 or 27 (lf_params.stencil 0 means 7).
 int stencil_of(const lf_params *p) { return p->stencil == 27 ? 27 : 7; }
 
@@ -73,6 +71,29 @@ int resident_blocks(const lf_params *p, int tile_x, int tile_y)
     (void)hipGetLastError();
     if (per_cu <= 0) per_cu = 3;
     return per_cu * cu_count();
+}
+
+// Automatic z-chunk of an LDS sweep over nz planes of N x N (N = p->N).
+// The whole grid resident at once (tiles march in lockstep and find their
+// neighbours' halo lines in L2).  The FP32 sweeps with 128-wide tiles do best
+// with two blocks per CU: a smaller L2 working set per XCD and long chunks
+// (7 points at 512^3: 256 planes, fetch 1.03x the algorithmic reads against
+// 1.16x with three blocks per CU and 64 planes; 256^3: 32 planes; 27 points:
+// 6% faster at 512^3 and 11% at 256^3 than 64-wide tiles filling the CUs).
+// The other sweeps fill the CUs and keep chunks of at most 64 planes.
+int auto_zchunk(const lf_params *p, int tile_x, int tile_y, int nz)
+{
+    const int N = p->N;
+    const bool two_per_cu = p->dtype == LF_F32 && tile_x == 128;
+    const int per_slab = ((N + tile_x - 1) / tile_x) * ((N + tile_y - 1) / tile_y);
+    const int res = resident_blocks(p, tile_x, tile_y);
+    const int target = two_per_cu && 2 * cu_count() < res ? 2 * cu_count() : res;
+    int nzc = target / per_slab;
+    nzc = nzc < 1 ? 1 : nzc;
+    int dz = (nz + nzc - 1) / nzc;
+    const int dz_max = two_per_cu ? nz : 64;
+    dz = dz < 8 ? 8 : (dz > dz_max ? dz_max : dz);
+    return dz < nz ? dz : nz;
 }
 
 Shape shape_of(const lf_params *p)
@@ -95,28 +116,7 @@ Shape shape_of(const lf_params *p)
         sh.rows = kRedBlocks;
         return sh;
     }
-    if (p->zchunk) {
-        sh.zchunk = p->zchunk < N ? p->zchunk : N;
-    } else {
-        // The whole grid resident at once (tiles march in lockstep and find
-        // their neighbours' halo lines in L2).  The FP32 sweeps with 128-wide
-        // tiles do best with two blocks per CU: a smaller L2 working set per
-        // XCD and long chunks (7 points at 512^3: 256 planes, fetch 1.03x the
-        // algorithmic reads against 1.16x with three blocks per CU and 64
-        // planes; 256^3: 32 planes; 27 points: 6% faster at 512^3 and 11% at
-        // 256^3 than 64-wide tiles filling the CUs).  The other sweeps fill
-        // the CUs and keep chunks of at most 64 planes.
-        const bool two_per_cu = p->dtype == LF_F32 && sh.tile_x == 128;
-        const int per_slab = ((N + sh.tile_x - 1) / sh.tile_x) * ((N + sh.tile_y - 1) / sh.tile_y);
-        const int res = resident_blocks(p, sh.tile_x, sh.tile_y);
-        const int target = two_per_cu && 2 * cu_count() < res ? 2 * cu_count() : res;
-        int nzc = target / per_slab;
-        nzc = nzc < 1 ? 1 : nzc;
-        int dz = (N + nzc - 1) / nzc;
-        const int dz_max = two_per_cu ? N : 64;
-        dz = dz < 8 ? 8 : (dz > dz_max ? dz_max : dz);
-        sh.zchunk = dz < N ? dz : N;
-    }
+    sh.zchunk = p->zchunk ? (p->zchunk < N ? p->zchunk : N) : auto_zchunk(p, sh.tile_x, sh.tile_y, N);
     sh.rows = sweep_lds_blocks(N, sh.tile_x, sh.tile_y, sh.zchunk);
     return sh;
 }
@@ -605,6 +605,88 @@ int lf_stream_copy(const float *a0, const float *a1, const float *a2, const floa
     for (int j = 0; j < 4; ++j)
         if ((rc = check_ptr(a[j], an[j])) || (rc = check_ptr(b[j], bn[j]))) return rc;
     launch_stream_copy(a, b, n, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return LF_OK;
+}
+
+// z-slab sweep: launch shape (the context's tiles, z-chunk zchunk or
+// automatic over nz planes) after the argument checks common to both calls.
+static int slab_shape(const lf_ctx *c, int nz, int zchunk, int *zeff, int64_t *rows)
+{
+    if (!c) return fail(LF_EINVAL, "ctx is NULL");
+    if (nz < 1 || nz > c->p.N) return fail(LF_EINVAL, "nz=%d: must be in [1, N=%d]", nz, c->p.N);
+    if (zchunk < 0) return fail(LF_EINVAL, "zchunk=%d: must be >= 0 (0 = automatic)", zchunk);
+    if (c->sh.tile_y == 1)
+        return fail(LF_EINVAL, "the slab sweep needs an LDS launch shape (tile_y 4, 8 or 16), not tile_y=1");
+    const int z = zchunk ? (zchunk < nz ? zchunk : nz) : auto_zchunk(&c->p, c->sh.tile_x, c->sh.tile_y, nz);
+    *zeff = z;
+    *rows = sweep_io_blocks(c->p.N, nz, c->sh.tile_x, c->sh.tile_y, z);
+    return LF_OK;
+}
+
+int lf_slab_rows(const lf_ctx *c, int nz, int zchunk, int64_t *rows)
+{
+    if (!rows) return fail(LF_EINVAL, "rows is NULL");
+    int z;
+    return slab_shape(c, nz, zchunk, &z, rows);
+}
+
+int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                  const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows)
+{
+    int z;
+    int64_t rows;
+    int rc = slab_shape(c, nz, zchunk, &z, &rows);
+    if (rc) return rc;
+    if (!in || !lo || !hi || !out) return fail(LF_EINVAL, "NULL pointer array");
+    if (!c->inited || c->hstep < 1)
+        return fail(LF_ESTATE, "lf_slab_sweep reuses the coefficients of the context's last step: "
+                               "take a step after lf_init / lf_set_state first");
+    if (!partials) return fail(LF_EINVAL, "partials is NULL");
+    if (partial_rows < rows)
+        return fail(LF_EINVAL, "partials holds %lld rows, the sweep writes %lld", (long long)partial_rows,
+                    (long long)rows);
+    const size_t es = esize(c->p.dtype), plane = (size_t)c->p.N * c->p.N * es;
+    // byte ranges: slab arrays nz planes, lower halo 2 planes (d) or 1 (e),
+    // upper halo 1 plane (d)
+    struct Range { const char *p; size_t n; const char *name; };
+    const char *names[14] = {"in[0]", "in[1]", "in[2]", "in[3]", "lo[0]", "lo[1]", "lo[2]", "lo[3]",
+                             "hi[0]", "hi[1]", "out[0]", "out[1]", "out[2]", "out[3]"};
+    Range r[14];
+    for (int i = 0; i < 4; ++i) {
+        r[i] = {(const char *)in[i], nz * plane, names[i]};
+        r[4 + i] = {(const char *)lo[i], (i < 2 ? 2 : 1) * plane, names[4 + i]};
+        r[10 + i] = {(const char *)out[i], nz * plane, names[10 + i]};
+    }
+    for (int i = 0; i < 2; ++i) r[8 + i] = {(const char *)hi[i], plane, names[8 + i]};
+    for (int i = 0; i < 14; ++i) {
+        if (!r[i].p) return fail(LF_EINVAL, "%s is NULL", r[i].name);
+        if ((uintptr_t)r[i].p % es) return fail(LF_EINVAL, "%s is not aligned to its element size", r[i].name);
+    }
+    // the outputs are written while neighbouring planes are still read: no
+    // output may overlap an input, a halo plane or another output
+    for (int i = 10; i < 14; ++i)
+        for (int j = 0; j < 14; ++j)
+            if (j != i && r[i].p < r[j].p + r[j].n && r[j].p < r[i].p + r[i].n)
+                return fail(LF_EINVAL, "%s overlaps %s", r[i].name, r[j].name);
+    SweepIO io{};
+    for (int i = 0; i < 4; ++i) {
+        io.in[i] = in[i];
+        io.out[i] = out[i];
+    }
+    // the sweep addresses plane z < 0 as lo + (z + 2) planes: e's halo holds
+    // plane -1 only, so its base sits one plane below (plane -2 of e is never read)
+    io.lo[0] = lo[0];
+    io.lo[1] = lo[1];
+    io.lo[2] = (const char *)lo[2] - plane;
+    io.lo[3] = (const char *)lo[3] - plane;
+    io.hi[0] = hi[0];
+    io.hi[1] = hi[1];
+    io.hi[2] = in[2];  // e is never read above the slab
+    io.hi[3] = in[3];
+    io.nz = nz;
+    launch_sweep_io(stencil_of(&c->p), c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, io, c->p.N, z, c->C,
+                    partials, c->stream);
     HIPCHK(hipGetLastError());
     return LF_OK;
 }

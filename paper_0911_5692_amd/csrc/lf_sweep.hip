@@ -91,13 +91,14 @@ __global__ void __launch_bounds__(256) k_sweep_plain(const T *__restrict__ d1, c
 
 // ------------------------------------------------------------ LDS z-march
 
-// One block's work: the tile x0.., y0.. of an N^3 lattice over planes
-// [z0, z1), writing its four partial sums to part_row[0..3].
+// One block's work: the tile x0.., y0.. of an N x N x zp.nz block over
+// planes [z0, z1), writing its four partial sums to part_row[0..3].
 template <typename T, int NH, int TX, int TY, int PF>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__restrict__ d2,
                                            const T *__restrict__ e1, const T *__restrict__ e2,
                                            T *__restrict__ d1n, T *__restrict__ d2n,
                                            T *__restrict__ e1n, T *__restrict__ e2n, const int N,
+                                           const ZPlanes<T> &zp,
                                            const int x0, const int y0, const int z0, const int z1,
                                            const CoefPair *__restrict__ C, double *__restrict__ part_row)
 {
@@ -160,12 +161,11 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         hoff[m] = wrapc(y0 + hly - 2) * N + wrapc(x0 + hlx - 2);
         hlsd[m] = hly * LW + hlx;
     }
-    // plane base pointers (uniform): global address = plane base + 32-bit offset;
-    // z stays within [z0 - 2, z1 + 1], so one conditional wrap suffices
-    auto plane = [&](const T *p, int z) {
-        const int zw = z < 0 ? z + N : (z >= N ? z - N : z);
-        return p + (int64_t)zw * NN;
-    };
+    // plane base pointers (uniform): global address = plane base + 32-bit
+    // offset.  Input i: z stays within [z0 - 2, z1 + 1] (planes past z1 are
+    // addressed but not read); outputs: planes [z0, z1)
+    auto plane = [&](int i, const T *p, int z) { return zp.at(i, p, z, NN); };
+    auto oplane = [&](T *p, int z) { return p + (int64_t)z * NN; };
 
     // register queues: d at z-1, z, z+1 and e at z, for both fields; PF
     // prefetch slots: slot j holds d(z+2+j), e(z+1+j) and the halo of plane
@@ -179,8 +179,8 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
     // chunk's needs are skipped
     auto fill = [&](int j, int pz) {
         const bool need_d = pz <= z1, need_e = pz - 1 <= z1 - 1, need_h = pz <= z1 - 1;
-        const T *a1 = plane(d1, pz), *a2 = plane(d2, pz);
-        const T *b1 = plane(e1, pz - 1), *b2 = plane(e2, pz - 1);
+        const T *a1 = plane(0, d1, pz), *a2 = plane(1, d2, pz);
+        const T *b1 = plane(2, e1, pz - 1), *b2 = plane(3, e2, pz - 1);
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             sd1[j][k] = need_d ? a1[goff[k]] : T(0);
@@ -199,10 +199,10 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
         }
     };
     {
-        const T *m1 = plane(d1, z0 - 2), *m2 = plane(d2, z0 - 2);
-        const T *c1p = plane(d1, z0 - 1), *c2p = plane(d2, z0 - 1);
-        const T *p1 = plane(d1, z0), *p2 = plane(d2, z0);
-        const T *f1 = plane(e1, z0 - 1), *f2 = plane(e2, z0 - 1);
+        const T *m1 = plane(0, d1, z0 - 2), *m2 = plane(1, d2, z0 - 2);
+        const T *c1p = plane(0, d1, z0 - 1), *c2p = plane(1, d2, z0 - 1);
+        const T *p1 = plane(0, d1, z0), *p2 = plane(1, d2, z0);
+        const T *f1 = plane(2, e1, z0 - 1), *f2 = plane(3, e2, z0 - 1);
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             qm1[k] = m1[goff[k]]; qm2[k] = m2[goff[k]];
@@ -243,8 +243,8 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
     int pz_st = 0;
     auto flush = [&]() {
         if (pend) {
-            T *o_e1 = const_cast<T *>(plane(e1n, pz_st)), *o_e2 = const_cast<T *>(plane(e2n, pz_st));
-            T *o_d1 = const_cast<T *>(plane(d1n, pz_st)), *o_d2 = const_cast<T *>(plane(d2n, pz_st));
+            T *o_e1 = oplane(e1n, pz_st), *o_e2 = oplane(e2n, pz_st);
+            T *o_d1 = oplane(d1n, pz_st), *o_d2 = oplane(d2n, pz_st);
 #pragma unroll
             for (int k = 0; k < KI; ++k)
                 if (act[k]) {
@@ -377,12 +377,14 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ d1, const T *__
 #define LF_SWEEP_PREFETCH 1
 #endif
 
-// Single lattice: one block per (tile, z-chunk), XCD-aware tile order.
+// Single lattice (or z-slab of one: zp): one block per (tile, z-chunk),
+// XCD-aware tile order.
 template <typename T, int NH, int TX, int TY>
 __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_lds(
     const T *__restrict__ d1, const T *__restrict__ d2, const T *__restrict__ e1, const T *__restrict__ e2,
     T *__restrict__ d1n, T *__restrict__ d2n, T *__restrict__ e1n, T *__restrict__ e2n, const int N,
-    const int zchunk, const int ntx, const int nty, const CoefPair *__restrict__ C, double *__restrict__ part)
+    const ZPlanes<T> zp, const int zchunk, const int ntx, const int nty, const CoefPair *__restrict__ C,
+    double *__restrict__ part)
 {
     // partial row = logical tile index (the ensemble kernel uses the same rows)
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -390,8 +392,8 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_lds(
     const int ty = b % nty;
     const int tz = b / nty;
     const int z0 = tz * zchunk;
-    sweep_tile<T, NH, TX, TY, LF_SWEEP_PREFETCH>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, tx * TX, ty * TY, z0,
-                              min(z0 + zchunk, N), C, part + (size_t)tile * kNPart);
+    sweep_tile<T, NH, TX, TY, LF_SWEEP_PREFETCH>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, zp, tx * TX, ty * TY,
+                                                 z0, min(z0 + zchunk, zp.nz), C, part + (size_t)tile * kNPart);
 }
 
 // Ensemble: a persistent grid walks a static list of work items
@@ -408,9 +410,10 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_ens(
         const int z0 = tz * e.zchunk;
         const T *const *in = (const T *const *)e.buf[parity];
         T *const *out = (T *const *)e.buf[parity ^ 1];
+        const ZPlanes<T> zp = periodic_planes<T>(in, e.N);
         sweep_tile<T, NH, TX, TY, LF_SWEEP_PREFETCH>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
-                                  tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
-                                  e.part + (size_t)it.z * kNPart);
+                                                     zp, tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
+                                                     e.part + (size_t)it.z * kNPart);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -454,46 +457,65 @@ void launch_sweep_plain(int stencil, int dtype, int beta, const void *const in[4
 
 int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk)
 {
-    return ((N + tile_x - 1) / tile_x) * ((N + tile_y - 1) / tile_y) * ((N + zchunk - 1) / zchunk);
+    return sweep_io_blocks(N, N, tile_x, tile_y, zchunk);
+}
+
+int sweep_io_blocks(int N, int nz, int tile_x, int tile_y, int zchunk)
+{
+    return ((N + tile_x - 1) / tile_x) * ((N + tile_y - 1) / tile_y) * ((nz + zchunk - 1) / zchunk);
+}
+
+SweepIO periodic_io(int dtype, const void *const in[4], void *const out[4], int N)
+{
+    SweepIO io{};
+    const int64_t plane_bytes = (int64_t)N * N * (dtype == 0 ? 4 : 8);
+    for (int i = 0; i < 4; ++i) {
+        io.in[i] = in[i];
+        io.lo[i] = (const char *)in[i] + (N - 2) * plane_bytes;
+        io.hi[i] = in[i];
+        io.out[i] = out[i];
+    }
+    io.nz = N;
+    return io;
 }
 
 template <typename T, int NH, int TX, int TY>
-static void sweep_lds_t(const void *const in[4], void *const out[4], int N, int zchunk,
-                        const CoefPair *C, double *part, hipStream_t st)
+static void sweep_lds_t(const SweepIO &io, int N, int zchunk, const CoefPair *C, double *part, hipStream_t st)
 {
-    const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY, nzc = (N + zchunk - 1) / zchunk;
+    const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY, nzc = (io.nz + zchunk - 1) / zchunk;
     hipLaunchKernelGGL((k_sweep_lds<T, NH, TX, TY>), dim3(ntx * nty * nzc), dim3(256), 0, st,
-                       (const T *)in[0], (const T *)in[1], (const T *)in[2], (const T *)in[3],
-                       (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3], N, zchunk, ntx, nty, C, part);
+                       (const T *)io.in[0], (const T *)io.in[1], (const T *)io.in[2], (const T *)io.in[3],
+                       (T *)io.out[0], (T *)io.out[1], (T *)io.out[2], (T *)io.out[3], N, planes_of<T>(io),
+                       zchunk, ntx, nty, C, part);
 }
 
 template <typename T, int TX, int TY>
-static void sweep_lds_b(int beta, const void *const in[4], void *const out[4], int N, int zchunk,
-                        const CoefPair *C, double *part, hipStream_t st)
+static void sweep_lds_b(int beta, const SweepIO &io, int N, int zchunk, const CoefPair *C, double *part,
+                        hipStream_t st)
 {
     switch (beta) {
-    case 2: sweep_lds_t<T, 1, TX, TY>(in, out, N, zchunk, C, part, st); break;
-    case 3: sweep_lds_t<T, 2, TX, TY>(in, out, N, zchunk, C, part, st); break;
-    case 4: sweep_lds_t<T, 3, TX, TY>(in, out, N, zchunk, C, part, st); break;
-    case 5: sweep_lds_t<T, 4, TX, TY>(in, out, N, zchunk, C, part, st); break;
-    default: sweep_lds_t<T, 5, TX, TY>(in, out, N, zchunk, C, part, st); break;
+    case 2: sweep_lds_t<T, 1, TX, TY>(io, N, zchunk, C, part, st); break;
+    case 3: sweep_lds_t<T, 2, TX, TY>(io, N, zchunk, C, part, st); break;
+    case 4: sweep_lds_t<T, 3, TX, TY>(io, N, zchunk, C, part, st); break;
+    case 5: sweep_lds_t<T, 4, TX, TY>(io, N, zchunk, C, part, st); break;
+    default: sweep_lds_t<T, 5, TX, TY>(io, N, zchunk, C, part, st); break;
     }
 }
 
 // Supported tiles (x by y): 64x4, 64x8, 64x16, 128x4, 128x8.
 template <typename T>
-static void sweep_lds_y(int tile_x, int tile_y, int beta, const void *const in[4], void *const out[4],
-                        int N, int zchunk, const CoefPair *C, double *part, hipStream_t st)
+static void sweep_lds_y(int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk,
+                        const CoefPair *C, double *part, hipStream_t st)
 {
     if (tile_x == 128) {
-        if (tile_y == 4) sweep_lds_b<T, 128, 4>(beta, in, out, N, zchunk, C, part, st);
-        else sweep_lds_b<T, 128, 8>(beta, in, out, N, zchunk, C, part, st);
+        if (tile_y == 4) sweep_lds_b<T, 128, 4>(beta, io, N, zchunk, C, part, st);
+        else sweep_lds_b<T, 128, 8>(beta, io, N, zchunk, C, part, st);
         return;
     }
     switch (tile_y) {
-    case 4: sweep_lds_b<T, 64, 4>(beta, in, out, N, zchunk, C, part, st); break;
-    case 8: sweep_lds_b<T, 64, 8>(beta, in, out, N, zchunk, C, part, st); break;
-    default: sweep_lds_b<T, 64, 16>(beta, in, out, N, zchunk, C, part, st); break;
+    case 4: sweep_lds_b<T, 64, 4>(beta, io, N, zchunk, C, part, st); break;
+    case 8: sweep_lds_b<T, 64, 8>(beta, io, N, zchunk, C, part, st); break;
+    default: sweep_lds_b<T, 64, 16>(beta, io, N, zchunk, C, part, st); break;
     }
 }
 
@@ -573,13 +595,20 @@ void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, 
     else sweep_ens_y<double>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
 }
 
+void launch_sweep_io(int stencil, int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N,
+                     int zchunk, const CoefPair *C, double *part, hipStream_t st)
+{
+    if (stencil == 27) launch_sweep_lds27(dtype, tile_x, tile_y, beta, io, N, zchunk, C, part, st);
+    else if (dtype == 0) sweep_lds_y<float>(tile_x, tile_y, beta, io, N, zchunk, C, part, st);
+    else sweep_lds_y<double>(tile_x, tile_y, beta, io, N, zchunk, C, part, st);
+}
+
 void launch_sweep_lds(int stencil, int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
                       void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
                       hipStream_t st)
 {
-    if (stencil == 27) launch_sweep_lds27(dtype, tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
-    else if (dtype == 0) sweep_lds_y<float>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
-    else sweep_lds_y<double>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+    launch_sweep_io(stencil, dtype, tile_x, tile_y, beta, periodic_io(dtype, in, out, N), N, zchunk, C, part,
+                    st);
 }
 
 }  // namespace lf

@@ -59,13 +59,14 @@ __device__ inline void st_nt(T v, T *base, unsigned boff)
     __builtin_nontemporal_store(v, (T *)((char *)base + boff));
 }
 
-// One block's work: tile (x0, y0) of an N^3 lattice over planes [z0, z1),
-// writing its four partial sums to part_row[0..3].
+// One block's work: tile (x0, y0) of an N x N x zp.nz block over planes
+// [z0, z1), writing its four partial sums to part_row[0..3].
 template <typename T, int NH, int TX, int TY>
 __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *__restrict__ d2,
                                              const T *__restrict__ e1, const T *__restrict__ e2,
                                              T *__restrict__ d1n, T *__restrict__ d2n,
                                              T *__restrict__ e1n, T *__restrict__ e2n, const int N,
+                                             const ZPlanes<T> &zp,
                                              const int x0, const int y0, const int z0, const int z1,
                                              const CoefPair *__restrict__ C, double *__restrict__ part_row)
 {
@@ -175,11 +176,10 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         hoff[m] = (unsigned)(wrapc(y0 + hly) * N + wrapc(x0 + hlx)) * sizeof(T);
         hlsd[m] = (hly + 2) * LW + hlx + 2;
     }
-    // plane base pointers: z stays within [z0 - 3, z1 + 2], one wrap suffices
-    auto plane = [&](const T *p, int z) {
-        const int zw = z < 0 ? z + N : (z >= N ? z - N : z);
-        return p + (int64_t)zw * NN;
-    };
+    // plane base pointers (uniform).  Inputs: d is read on planes
+    // [z0 - 2, z1], e on [z0 - 1, z1 - 1]; outputs: planes [z0, z1)
+    auto plane = [&](int i, const T *p, int z) { return zp.at(i, p, z, NN); };
+    auto oplane = [&](T *p, int z) { return p + (int64_t)z * NN; };
 
     // Registers per site and field: d(z) qc, d(z+1) qp, d(z+2) nd (staged this
     // iteration), e(z) ev, partial sums A(z-1) am, A(z) ac, B(z) bc; loads in
@@ -192,8 +192,8 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
 
     const int zs = z0 - 3;  // first iteration: plane z0-2 staged
     {
-        const T *a1 = plane(d1, z0 - 2), *a2 = plane(d2, z0 - 2);
-        const T *b1 = plane(d1, z0 - 1), *b2 = plane(d2, z0 - 1);
+        const T *a1 = plane(0, d1, z0 - 2), *a2 = plane(1, d2, z0 - 2);
+        const T *b1 = plane(0, d1, z0 - 1), *b2 = plane(1, d2, z0 - 1);
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             qp1[k] = ld_at(a1, goff[k]); qp2[k] = ld_at(a2, goff[k]);
@@ -231,8 +231,8 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
     int pz_st = 0;
     auto flush = [&]() {
         if (pend) {
-            T *o_e1 = const_cast<T *>(plane(e1n, pz_st)), *o_e2 = const_cast<T *>(plane(e2n, pz_st));
-            T *o_d1 = const_cast<T *>(plane(d1n, pz_st)), *o_d2 = const_cast<T *>(plane(d2n, pz_st));
+            T *o_e1 = oplane(e1n, pz_st), *o_e2 = oplane(e2n, pz_st);
+            T *o_d1 = oplane(d1n, pz_st), *o_d2 = oplane(d2n, pz_st);
 #pragma unroll
             for (int k = 0; k < KI; ++k)
                 if (act[k]) {
@@ -266,8 +266,8 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             // chunk does not need are never used
             const int pz = min(z + 3, z1);
             const int pe = min(max(z + 1, z0 - 1), z1 - 1);
-            const T *a1 = plane(d1, pz), *a2 = plane(d2, pz);
-            const T *b1 = plane(e1, pe), *b2 = plane(e2, pe);
+            const T *a1 = plane(0, d1, pz), *a2 = plane(1, d2, pz);
+            const T *b1 = plane(2, e1, pe), *b2 = plane(3, e2, pe);
 #pragma unroll
             for (int k = 0; k < KI; ++k) {
                 ld1[k] = ld_at(a1, goff[k]);
@@ -458,15 +458,16 @@ template <typename T, int NH, int TX, int TY>
 __global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_lds27(
     const T *__restrict__ d1, const T *__restrict__ d2, const T *__restrict__ e1, const T *__restrict__ e2,
     T *__restrict__ d1n, T *__restrict__ d2n, T *__restrict__ e1n, T *__restrict__ e2n, const int N,
-    const int zchunk, const int ntx, const int nty, const CoefPair *__restrict__ C, double *__restrict__ part)
+    const ZPlanes<T> zp, const int zchunk, const int ntx, const int nty, const CoefPair *__restrict__ C,
+    double *__restrict__ part)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % ntx, b = tile / ntx;
     const int ty = b % nty;
     const int tz = b / nty;
     const int z0 = tz * zchunk;
-    sweep_tile27<T, NH, TX, TY>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, tx * TX, ty * TY, z0,
-                                min(z0 + zchunk, N), C, part + (size_t)tile * kNPart);
+    sweep_tile27<T, NH, TX, TY>(d1, d2, e1, e2, d1n, d2n, e1n, e2n, N, zp, tx * TX, ty * TY, z0,
+                                min(z0 + zchunk, zp.nz), C, part + (size_t)tile * kNPart);
 }
 
 template <typename T, int NH, int TX, int TY>
@@ -480,7 +481,8 @@ __global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_ens27(
         const int z0 = tz * e.zchunk;
         const T *const *in = (const T *const *)e.buf[parity];
         T *const *out = (T *const *)e.buf[parity ^ 1];
-        sweep_tile27<T, NH, TX, TY>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
+        const ZPlanes<T> zp = periodic_planes<T>(in, e.N);
+        sweep_tile27<T, NH, TX, TY>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N, zp,
                                     tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
                                     e.part + (size_t)it.z * kNPart);
         __syncthreads();  // LDS is reused by the next item
@@ -523,18 +525,18 @@ void with_tile(int tile_x, int tile_y, F &&f)
 }
 
 template <typename T>
-void lds27_t(int tile_x, int tile_y, int beta, const void *const in[4], void *const out[4], int N,
-             int zchunk, const CoefPair *C, double *part, hipStream_t st)
+void lds27_t(int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk, const CoefPair *C,
+             double *part, hipStream_t st)
 {
     with_tile(tile_x, tile_y, [&](auto tx, auto ty) {
         constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
         with_nh(beta, [&](auto nh) {
             constexpr int NH = decltype(nh)::value;
-            const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY, nzc = (N + zchunk - 1) / zchunk;
+            const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY, nzc = (io.nz + zchunk - 1) / zchunk;
             hipLaunchKernelGGL((k_sweep_lds27<T, NH, TX, TY>), dim3(ntx * nty * nzc), dim3(256), 0, st,
-                               (const T *)in[0], (const T *)in[1], (const T *)in[2], (const T *)in[3],
-                               (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3], N, zchunk, ntx, nty, C,
-                               part);
+                               (const T *)io.in[0], (const T *)io.in[1], (const T *)io.in[2],
+                               (const T *)io.in[3], (T *)io.out[0], (T *)io.out[1], (T *)io.out[2],
+                               (T *)io.out[3], N, planes_of<T>(io), zchunk, ntx, nty, C, part);
         });
     });
 }
@@ -570,12 +572,11 @@ int occ27_t(int tile_x, int tile_y, int beta)
 
 }  // namespace
 
-void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
-                        void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
-                        hipStream_t st)
+void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk,
+                        const CoefPair *C, double *part, hipStream_t st)
 {
-    if (dtype == 0) lds27_t<float>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
-    else lds27_t<double>(tile_x, tile_y, beta, in, out, N, zchunk, C, part, st);
+    if (dtype == 0) lds27_t<float>(tile_x, tile_y, beta, io, N, zchunk, C, part, st);
+    else lds27_t<double>(tile_x, tile_y, beta, io, N, zchunk, C, part, st);
 }
 
 void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,

@@ -284,6 +284,37 @@ class Lattice:
         check(lib().lf_set_state(self._ctx, *ptrs, ctypes.byref(scalars)))
 
 
+    # ------------------------------------------------------------ z-slab share
+    def slab_rows(self, nz: int, zchunk: int = 0) -> int:
+        """Partial-sum rows lf_slab_sweep writes for a slab of nz planes."""
+        rows = ctypes.c_int64()
+        check(lib().lf_slab_rows(self._ctx, int(nz), int(zchunk), ctypes.byref(rows)))
+        return rows.value
+
+    def slab_sweep(self, slab, lo, hi, out=None, zchunk: int = 0):
+        """One step's sweep on a z-slab of this lattice with halo planes
+        (lf_slab_sweep): slab = (d1, d2, e1, e2), each (nz, N, N) in the
+        stored deviation form; lo = (d1, d2 of planes -2, -1; e1, e2 of plane
+        -1); hi = (d1, d2 of plane nz).  Uses the coefficients of the last
+        step.  Returns (out arrays, partial rows (rows, 4) float64);
+        asynchronous on the lattice's stream."""
+        N, dt, dev = self.N, self.dtype, self.ws.device
+        nz = int(slab[0].shape[0])
+        want = [(nz, N, N)] * 4
+        lo_shapes = [(2, N, N), (2, N, N), (1, N, N), (1, N, N)]
+        for t, shp in zip((*slab, *lo, *hi), want + lo_shapes + [(1, N, N)] * 2):
+            if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
+                raise ValueError(f"slab arrays: contiguous {dt} tensors of shape {shp} on {dev}")
+        if out is None:
+            out = tuple(torch.empty((nz, N, N), dtype=dt, device=dev) for _ in range(4))
+        rows = self.slab_rows(nz, zchunk)
+        part = torch.empty((rows, 4), dtype=torch.float64, device=dev)
+        arr = lambda ts: (ctypes.c_void_p * len(ts))(*(t.data_ptr() for t in ts))
+        check(lib().lf_slab_sweep(self._ctx, nz, int(zchunk), arr(slab), arr(lo), arr(hi), arr(out),
+                                  ctypes.c_void_p(part.data_ptr()), rows))
+        self._keep = (slab, lo, hi, out, part)
+        return out, part
+
     # ------------------------------------------------------------ adjoint
     def adjoint_forward(self, n: int, K: int, weights=(0.0, 1.0, 0.0, 1.0)) -> float:
         """Run n steps with checkpoints every K steps; returns the loss

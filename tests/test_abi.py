@@ -154,3 +154,13 @@ def test_stream_copy_arguments_checked_before_any_device_call(LB):
     assert "b3" in lib.lf_last_error().decode()
     assert lib.lf_stream_copy(p, ctypes.c_void_p(0x100004), p, p, p, p, p, p, 8, None) == LB.LF_EINVAL
     assert "a1" in lib.lf_last_error().decode()
+
+
+def test_slab_sweep_arguments_checked_before_any_device_call(LB):
+    lib = LB.lib()
+    rows = ctypes.c_int64()
+    assert lib.lf_slab_rows(None, 8, 0, ctypes.byref(rows)) == LB.LF_EINVAL
+    assert "ctx" in lib.lf_last_error().decode()
+    p = (ctypes.c_void_p * 4)(0x100000, 0x100000, 0x100000, 0x100000)
+    assert lib.lf_slab_sweep(None, 8, 0, p, p, p, p, ctypes.c_void_p(0x100000), 1 << 20) == LB.LF_EINVAL
+    assert "ctx" in lib.lf_last_error().decode()
