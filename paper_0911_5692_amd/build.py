@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblf.so")
-SOURCES = ["lf_api.hip", "lf_kernels.hip", "lf_sweep.hip", "lf_sweep27.hip", "lf_adjoint.hip", "lf_fft.hip"]
+SOURCES = ["lf_api.hip", "lf_kernels.hip", "lf_sweep.hip", "lf_sweep27.hip", "lf_slab7.hip", "lf_slab27.hip",
+           "lf_adjoint.hip", "lf_fft.hip"]
 LIBS = ["-L/opt/rocm/lib", "-lhipfft"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

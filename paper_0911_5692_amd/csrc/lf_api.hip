@@ -674,19 +674,21 @@ int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const 
         io.in[i] = in[i];
         io.out[i] = out[i];
     }
-    // the sweep addresses plane z < 0 as lo + (z + 2) planes: e's halo holds
-    // plane -1 only, so its base sits one plane below (plane -2 of e is never read)
+    // halo bases: the sweep addresses plane z < 0 of input i at lo + (z + 2)
+    // planes and plane z >= nz at hi + (z - nz) planes.  e's lower halo holds
+    // plane -1 only, so its base sits one plane below (plane -2 of e is never
+    // read); e is never read above the slab
     io.lo[0] = lo[0];
     io.lo[1] = lo[1];
     io.lo[2] = (const char *)lo[2] - plane;
     io.lo[3] = (const char *)lo[3] - plane;
     io.hi[0] = hi[0];
     io.hi[1] = hi[1];
-    io.hi[2] = in[2];  // e is never read above the slab
+    io.hi[2] = in[2];
     io.hi[3] = in[3];
     io.nz = nz;
-    launch_sweep_io(stencil_of(&c->p), c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, io, c->p.N, z, c->C,
-                    partials, c->stream);
+    launch_sweep_slab(stencil_of(&c->p), c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, io, c->p.N, z,
+                      c->C, partials, c->stream);
     HIPCHK(hipGetLastError());
     return LF_OK;
 }

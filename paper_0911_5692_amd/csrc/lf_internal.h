@@ -89,7 +89,7 @@ void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, 
                       const int4 *items, int nitems, int grid, int parity, hipStream_t st);
 void launch_sweep_plain(int stencil, int dtype, int beta, const void *const in[4], void *const out[4], int N,
                         const CoefPair *C, hipStream_t st);
-// Arrays of one LDS sweep over planes [0, nz) of an N x N x nz block: the
+// Arrays of one sweep over planes [0, nz) of an N x N x nz z-slab: the
 // inputs d1, d2, e1, e2, their halo bases (lo: plane -2, hi: plane nz; see
 // ZPlanes in lf_sweep_common.h) and the outputs.
 struct SweepIO {
@@ -99,20 +99,23 @@ struct SweepIO {
     void *out[4];
     int nz;
 };
-// The periodic N^3 lattice: halo bases inside the input arrays themselves.
-SweepIO periodic_io(int dtype, const void *const in[4], void *const out[4], int N);
 void launch_sweep_lds(int stencil, int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
                       void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
                       hipStream_t st);
-void launch_sweep_io(int stencil, int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N,
-                     int zchunk, const CoefPair *C, double *part, hipStream_t st);
+// z-slab sweeps (lf_slab7.hip, lf_slab27.hip); launch_sweep_slab dispatches
+// to launch_sweep_slab27 for stencil 27
+void launch_sweep_slab(int stencil, int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N,
+                       int zchunk, const CoefPair *C, double *part, hipStream_t st);
+void launch_sweep_slab27(int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk,
+                         const CoefPair *C, double *part, hipStream_t st);
 int sweep_lds_blocks(int N, int tile_x, int tile_y, int zchunk);
 // blocks (= partial rows) of a sweep over nz planes of an N x N x nz block
 int sweep_io_blocks(int N, int nz, int tile_x, int tile_y, int zchunk);
-// 27-point LDS sweep (lf_sweep27.hip); launch_sweep_io / launch_sweep_ens /
+// 27-point LDS sweep (lf_sweep27.hip); launch_sweep_lds / launch_sweep_ens /
 // sweep_lds_blocks_per_cu dispatch to these for stencil 27.
-void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk,
-                        const CoefPair *C, double *part, hipStream_t st);
+void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void *const in[4],
+                        void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
+                        hipStream_t st);
 void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
                         const int4 *items, int nitems, int grid, int parity, hipStream_t st);
 int sweep_lds27_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);

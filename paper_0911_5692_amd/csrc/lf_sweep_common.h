@@ -58,13 +58,12 @@ __device__ inline double potential_pow(double x)
     return r;
 }
 
-// Where the z-planes of the four input arrays (d1, d2, e1, e2) lie.  A sweep
-// reads d on planes [z0-2, z1] and e on [z0-1, z1-1] of a chunk [z0, z1) of
-// [0, nz).  Planes 0 .. nz-1 are the arrays' own; plane z < 0 lies at
-// lo[i] + (z+2) N^2 and plane z >= nz at hi[i] + (z-nz) N^2.  A periodic
-// lattice (nz = N) points lo at its own plane N-2 and hi at its plane 0; a
-// z-slab of a larger lattice points them at halo planes received from its
-// neighbours (e is never read above the slab).
+// Where the z-planes of the four input arrays (d1, d2, e1, e2) of a z-slab
+// sweep lie.  A sweep reads d on planes [z0-2, z1] and e on [z0-1, z1-1] of
+// a chunk [z0, z1) of [0, nz).  Planes 0 .. nz-1 are the arrays' own; plane
+// z < 0 lies at lo[i] + (z+2) N^2 and plane z >= nz at hi[i] + (z-nz) N^2,
+// in the slab's halo buffers (e is never read above the slab).  Only the
+// slab kernels use this; the periodic ones wrap the plane index.
 template <typename T>
 struct ZPlanes {
     const T *lo[4];
@@ -76,19 +75,6 @@ struct ZPlanes {
                      : (z >= nz ? hi[i] + (int64_t)(z - nz) * NN : p + (int64_t)z * NN);
     }
 };
-
-template <typename T>
-__host__ __device__ inline ZPlanes<T> periodic_planes(const T *const in[4], int N)
-{
-    ZPlanes<T> zp;
-    const int64_t NN = (int64_t)N * N;
-    for (int i = 0; i < 4; ++i) {
-        zp.lo[i] = in[i] + (int64_t)(N - 2) * NN;
-        zp.hi[i] = in[i];
-    }
-    zp.nz = N;
-    return zp;
-}
 
 template <typename T>
 inline ZPlanes<T> planes_of(const SweepIO &io)

@@ -41,8 +41,8 @@ def _code_only(text: str) -> str:
 def sweep_source_hash(stencil: int = 7) -> str:
     """Hash of the code (comments aside) of the sweep kernel of this stencil."""
     h = hashlib.sha256()
-    main = "lf_sweep27.hip" if stencil == 27 else "lf_sweep.hip"
-    for f in (main, "lf_sweep_common.h", "lf_internal.h", "lf_stencil.h"):
+    main = ("lf_sweep27.hip", "lf_sweep27_tile.h") if stencil == 27 else ("lf_sweep.hip", "lf_sweep_tile.h")
+    for f in (*main, "lf_sweep_common.h", "lf_internal.h", "lf_stencil.h"):
         with open(os.path.join(PKG, "csrc", f)) as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
