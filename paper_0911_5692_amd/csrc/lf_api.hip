@@ -213,10 +213,11 @@ namespace {
 // One leapfrog step: FP64 scale-factor update from the pending partial sums,
 // then the fused kick-drift sweep from the arrays `in` into `out`, which
 // leaves the partial sums of the new fields for the next step.
-void enqueue_step_io(lf_ctx *c, const void *const in[4], void *const out[4], hipStream_t st, hipEvent_t *ev)
+void enqueue_step_io(lf_ctx *c, const void *const in[4], void *const out[4], hipStream_t st, hipEvent_t *ev,
+                     DevScalars *tape = nullptr)
 {
     if (ev) (void)hipEventRecord(ev[0], st);
-    launch_aupdate(c->part, c->sh.rows, c->P, c->S, c->C, st);
+    launch_aupdate(c->part, c->sh.rows, c->P, c->S, c->C, st, tape);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (c->sh.tile_y == 1) {
         launch_sweep_plain(stencil_of(&c->p), c->p.dtype, c->p.beta, in, out, c->p.N, c->C, st);
@@ -858,13 +859,16 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
         // needed
         if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, ws + L.seg, L))) return rc;
         const int64_t m = (n - s * K) < K ? (n - s * K) : K;
+        // (the scale-factor kernel of step j writes tape j; the segment's
+        // last state, whose step is skipped, is copied)
         for (int64_t j = 0; j < m; ++j) {
-            HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
             if (j + 1 < m) {
                 char *a = ws + L.seg + (size_t)j * 4 * L.arr_bytes, *b = a + 4 * L.arr_bytes;
                 const void *in[4] = {a, a + L.arr_bytes, a + 2 * L.arr_bytes, a + 3 * L.arr_bytes};
                 void *out[4] = {b, b + L.arr_bytes, b + 2 * L.arr_bytes, b + 3 * L.arr_bytes};
-                enqueue_step_io(c, in, out, c->stream, nullptr);
+                enqueue_step_io(c, in, out, c->stream, nullptr, tape + j);
+            } else {
+                HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
             }
         }
         // reverse steps; inside a segment the fields pass of step j also

@@ -82,8 +82,9 @@ void launch_init_fields(int dtype, int in_dtype, const void *f1, const void *f2,
                         const DevParams *P, const DevScalars *S, hipStream_t st);
 void launch_reduce(int stencil, int dtype, const void *d1, const void *d2, int N, const double *bg_f,
                    int beta, double *part, int nblk, hipStream_t st);
+// tape (may be NULL): receives a copy of *S as it was before the update
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S,
-                    CoefPair *C, hipStream_t st);
+                    CoefPair *C, hipStream_t st, DevScalars *tape = nullptr);
 void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st);
 void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
                       const int4 *items, int nitems, int grid, int parity, hipStream_t st);

@@ -224,7 +224,7 @@ __device__ inline double binom_d(int n, int k)
 //   a'_{k+1/2} = (a'_k + a'_{k+1})/2, a''_{k+1/2} = (a'_{k+1} - a'_k)/dt,
 //   a_{k+3/2} = a_{k+1/2} + dt a'_{k+1}.
 __device__ void aupdate_block(const double *part, int nblk, const DevParams *__restrict__ P,
-                              DevScalars *S, CoefPair *C)
+                              DevScalars *S, CoefPair *C, DevScalars *tape)
 {
     double t[kNPart];
     stage2_sum<kNPart>(part, nblk, t);
@@ -242,6 +242,7 @@ __device__ void aupdate_block(const double *part, int nblk, const DevParams *__r
     const double ap1 = __shfl(pw, 0, 64), ap2 = __shfl(pw, 1, 64), aF = __shfl(pw, 2, 64);
     const double aV = __shfl(pw, 3, 64), alpha = __shfl(pw, 4, 64);
     if (l != 0) return;
+    if (tape) *tape = *S;  // the scalars before this step (the adjoint's tape)
     const double Sg = P->gw * (t[0] + t[1]) / (dx * dx * N3);
     const double SV = (c1 * ap1 * t[2] / (double)beta + 0.5 * G * ap2 * t[3]) / N3;
     const double Fa = P->kappa2 * aF * (Sg / 3.0 + aV * SV);
@@ -290,16 +291,16 @@ __device__ void aupdate_block(const double *part, int nblk, const DevParams *__r
 
 __global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, int nblk,
                                                             const DevParams *__restrict__ P,
-                                                            DevScalars *S, CoefPair *C)
+                                                            DevScalars *S, CoefPair *C, DevScalars *tape)
 {
-    aupdate_block(part, nblk, P, S, C);
+    aupdate_block(part, nblk, P, S, C, tape);
 }
 
 // Ensemble: block r updates realization r.
 __global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *tab)
 {
     const EnsEntry &e = tab[blockIdx.x];
-    aupdate_block(e.part, e.rows, e.P, e.S, e.Cw);
+    aupdate_block(e.part, e.rows, e.P, e.S, e.Cw, nullptr);
 }
 
 // ---------------------------------------------------------------- energies
@@ -654,9 +655,9 @@ void launch_reduce(int stencil, int dtype, const void *d1, const void *d2, int N
 }
 
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S, CoefPair *C,
-                    hipStream_t st)
+                    hipStream_t st, DevScalars *tape)
 {
-    hipLaunchKernelGGL(k_aupdate, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, C);
+    hipLaunchKernelGGL(k_aupdate, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, C, tape);
 }
 
 void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st)
