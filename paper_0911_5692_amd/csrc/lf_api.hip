@@ -667,9 +667,11 @@ int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const 
     // the outputs are written while neighbouring planes are still read: no
     // output may overlap an input, a halo plane or another output
     for (int i = 10; i < 14; ++i)
-        for (int j = 0; j < 14; ++j)
-            if (j != i && r[i].p < r[j].p + r[j].n && r[j].p < r[i].p + r[i].n)
+        for (int j = 0; j < 14; ++j) {
+            const uintptr_t a = (uintptr_t)r[i].p, b = (uintptr_t)r[j].p;
+            if (j != i && a < b + r[j].n && b < a + r[i].n)
                 return fail(LF_EINVAL, "%s overlaps %s", r[i].name, r[j].name);
+        }
     SweepIO io{};
     for (int i = 0; i < 4; ++i) {
         io.in[i] = in[i];

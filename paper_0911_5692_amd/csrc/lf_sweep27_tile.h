@@ -277,7 +277,9 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
         const T *s0 = sd[cur][0], *s1 = sd[cur][1];
         T *n0 = sn[nb_cur][0], *n1 = sn[nb_cur][1];
         T an1[KI], an2[KI], bn1[KI], bn2[KI], na1[KI], na2[KI];
-        // partial sums of the staged plane z+1, and the update of plane z
+        // partial sums of the staged plane z+1 (explicit fma: the ring
+        // sites below repeat the same expression, so a ring value equals the
+        // neighbouring tile's stored value bitwise), and the update of plane z
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             const int l = lsd[k];
@@ -285,15 +287,15 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             const T g1 = (s0[l - LW - 1] + s0[l - LW + 1]) + (s0[l + LW - 1] + s0[l + LW + 1]);
             const T f2 = (s1[l - 1] + s1[l + 1]) + (s1[l - LW] + s1[l + LW]);
             const T g2 = (s1[l - LW - 1] + s1[l - LW + 1]) + (s1[l + LW - 1] + s1[l + LW + 1]);
-            an1[k] = (T(14) * qp1[k] + T(3) * f1) + g1;
-            bn1[k] = (T(-128) * qp1[k] + T(14) * f1) + T(3) * g1;
-            an2[k] = (T(14) * qp2[k] + T(3) * f2) + g2;
-            bn2[k] = (T(-128) * qp2[k] + T(14) * f2) + T(3) * g2;
+            an1[k] = fma(T(14), qp1[k], fma(T(3), f1, g1));
+            bn1[k] = fma(T(-128), qp1[k], fma(T(14), f1, T(3) * g1));
+            an2[k] = fma(T(14), qp2[k], fma(T(3), f2, g2));
+            bn2[k] = fma(T(-128), qp2[k], fma(T(14), f2, T(3) * g2));
             T ia, ib;
-            c.force(qc1[k], qc2[k], (bc1[k] + am1[k]) + an1[k], (bc2[k] + am2[k]) + an2[k], ia, ib);
+            c.force_fma(qc1[k], qc2[k], (bc1[k] + am1[k]) + an1[k], (bc2[k] + am2[k]) + an2[k], ia, ib);
             const T ea = ev1[k] + ia, eb = ev2[k] + ib;
-            na1[k] = qc1[k] + c.dt * ea;
-            na2[k] = qc2[k] + c.dt * eb;
+            na1[k] = fma(c.dt, ea, qc1[k]);
+            na2[k] = fma(c.dt, eb, qc2[k]);
             pe1[k] = ea; pe2[k] = eb; pd1[k] = na1[k]; pd2[k] = na2[k];
             // planes below z0-1 are written too: their slots are rewritten
             // before the first read
@@ -307,14 +309,14 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             const T g1 = (s0[l - LW - 1] + s0[l - LW + 1]) + (s0[l + LW - 1] + s0[l + LW + 1]);
             const T f2 = (s1[l - 1] + s1[l + 1]) + (s1[l - LW] + s1[l + LW]);
             const T g2 = (s1[l - LW - 1] + s1[l - LW + 1]) + (s1[l + LW - 1] + s1[l + LW + 1]);
-            ran1 = (T(14) * rqp1 + T(3) * f1) + g1;
-            rbn1 = (T(-128) * rqp1 + T(14) * f1) + T(3) * g1;
-            ran2 = (T(14) * rqp2 + T(3) * f2) + g2;
-            rbn2 = (T(-128) * rqp2 + T(14) * f2) + T(3) * g2;
+            ran1 = fma(T(14), rqp1, fma(T(3), f1, g1));
+            rbn1 = fma(T(-128), rqp1, fma(T(14), f1, T(3) * g1));
+            ran2 = fma(T(14), rqp2, fma(T(3), f2, g2));
+            rbn2 = fma(T(-128), rqp2, fma(T(14), f2, T(3) * g2));
             T ia, ib;
-            c.force(rqc1, rqc2, (rbc1 + ram1) + ran1, (rbc2 + ram2) + ran2, ia, ib);
-            rna1 = rqc1 + c.dt * (rev1 + ia);
-            rna2 = rqc2 + c.dt * (rev2 + ib);
+            c.force_fma(rqc1, rqc2, (rbc1 + ram1) + ran1, (rbc2 + ram2) + ran2, ia, ib);
+            rna1 = fma(c.dt, rev1 + ia, rqc1);
+            rna2 = fma(c.dt, rev2 + ib, rqc2);
             n0[rlsn] = rna1;
             n1[rlsn] = rna2;
         }
@@ -337,18 +339,25 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
             const T *m0 = sn[nb_prev][0], *m1 = sn[nb_prev][1];    // plane z-1
             // bonds of interior site k; a bond that is not this block's
             // reads the site's own slot and is multiplied by 0 (no branch)
+            // The sums of squares are written as explicit fma chains: the
+            // three phase copies of this loop then round a site's term
+            // identically, so the step sums do not depend on where a chunk
+            // starts (left to contraction, they differed in FP32 in the
+            // last bits).
             auto bonds = [&](const T *P, const T *M, const int l, const T v, const int k) {
-                auto sq = [&](T u) { const T d = v - u; return d * d; };
-                auto sqm = [&](T u, T msk) { const T d = (v - u) * msk; return d * d; };
-                const T F = (sq(P[l - 1]) + sq(P[l - NW])) + sq(M[l]);
+                auto df = [&](T u) { return v - u; };
+                auto dm = [&](T u, T msk) { return (v - u) * msk; };
+                const T f0 = df(P[l - 1]), f1 = df(P[l - NW]), f2 = df(M[l]);
+                const T F = fma(f0, f0, fma(f1, f1, f2 * f2));
                 // a (+1,-1) bond that is not the block's reads the site's own
                 // slot of plane z, which holds v: its difference is exactly 0
-                T E = sq(P[l - NW - 1]) + sq(P[ix4[k]]);
-                E += sq(M[l - 1]) + sq(M[l - NW]);
-                E += sqm(M[ixx[k]], mx[k]) + sqm(M[ixy[k]], my[k]);
-                T Cn = sq(M[l - NW - 1]) + sqm(M[ix4[k]], m4[k]);
-                Cn += sqm(M[ixyl[k]], my[k]) + sqm(M[ixxy[k]], mxy[k]);
-                return (double)((T(14) * F + T(3) * E) + Cn);
+                const T e0 = df(P[l - NW - 1]), e1 = df(P[ix4[k]]), e2 = df(M[l - 1]), e3 = df(M[l - NW]);
+                const T e4 = dm(M[ixx[k]], mx[k]), e5 = dm(M[ixy[k]], my[k]);
+                const T E = fma(e0, e0, fma(e1, e1, fma(e2, e2, fma(e3, e3, fma(e4, e4, e5 * e5)))));
+                const T c0 = df(M[l - NW - 1]), c1 = dm(M[ix4[k]], m4[k]);
+                const T c2 = dm(M[ixyl[k]], my[k]), c3 = dm(M[ixxy[k]], mxy[k]);
+                const T Cn = fma(c0, c0, fma(c1, c1, fma(c2, c2, c3 * c3)));
+                return (double)fma(T(14), F, fma(T(3), E, Cn));
             };
 #pragma unroll
             for (int k = 0; k < KI; ++k) {
@@ -364,10 +373,11 @@ __device__ __forceinline__ void sweep_tile27(const T *__restrict__ d1, const T *
                 // bonds that are not this block's read the ring's own slot
                 // (rq, rqi = rlsn) and are multiplied by 0
                 auto rb = [&](const T *P, const T *M, const T v) {
-                    auto sqm = [&](T u, T msk) { const T d = (v - u) * msk; return d * d; };
-                    const T E = sqm(M[rq[1]], rv[1]) + sqm(P[rqi], rvi);
-                    const T Cn = sqm(M[rq[0]], rv[0]) + sqm(M[rq[2]], rv[2]);
-                    return (double)(T(3) * E + Cn);
+                    auto dm = [&](T u, T msk) { return (v - u) * msk; };
+                    const T e0 = dm(M[rq[1]], rv[1]), e1 = dm(P[rqi], rvi);
+                    const T c0 = dm(M[rq[0]], rv[0]), c1 = dm(M[rq[2]], rv[2]);
+                    const T E = fma(e0, e0, e1 * e1), Cn = fma(c0, c0, c1 * c1);
+                    return (double)fma(T(3), E, Cn);
                 };
                 acc0 += rb(p0, m0, rna1);
                 acc1 += rb(p1, m1, rna2);

@@ -41,6 +41,21 @@ struct Coefs {
         inc_a = (Cl * s6a + Cf * a) - dv1;
         inc_b = (Cl * s6b + Cf * b) - dv2;
     }
+    // The same increments with every multiply-add an explicit fma, so that
+    // each inlined copy rounds alike whatever the compiler would contract
+    // (the 27-point sweep computes a site in several copies of its loop and,
+    // redundantly, as another tile's ring site).
+    __device__ inline void force_fma(T a, T b, T s6a, T s6b, T &inc_a, T &inc_b) const
+    {
+        T hor = h[NH - 1];
+#pragma unroll
+        for (int j = NH - 2; j >= 0; --j) hor = fma(hor, a, h[j]);
+        const T t2 = g2 + b;
+        const T dv1 = fma(hor, a, C2 * fma(a * t2, t2, (g1 * b) * (two_g2 + b)));
+        const T dv2 = C2 * fma(a * (two_g1 + a), t2, g1sq * b);
+        inc_a = fma(Cl, s6a, fma(Cf, a, -dv1));
+        inc_b = fma(Cl, s6b, fma(Cf, b, -dv2));
+    }
 };
 
 template <typename T>

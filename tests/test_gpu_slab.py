@@ -36,15 +36,13 @@ def _halos(state, zb, ze, N):
     return lo, hi
 
 
-# Bound on the relative difference of the step sums between two z-chunkings.
-# The 27-point sweep forms each site's bond sum in the working precision, in
-# three phase-specialised copies of its z loop; the chunk start decides which
-# copy runs a plane, and the copies may contract the sum into FMAs
-# differently, so in FP32 a site's term can change in its last bits (about
-# 1e-7 of one term; the total moves by far less).  FP64 terms, and the
-# 7-point sweep's FP64 differences, leave only the summation order.
+# Bound on the relative difference of the step sums between two z-chunkings
+# of the same step: the same per-site terms summed in another order (FP64).
+# The 27-point sweep runs its z loop in three phase-specialised copies; its
+# per-site bond sums are explicit fma chains, so every copy rounds a site's
+# term the same way and the FP32 terms do not depend on where a chunk starts.
 def _sum_tol(lat):
-    return 1e-6 if (lat.dtype == F32 and lat.params.stencil == 27) else 1e-12
+    return 1e-12
 
 
 def _check_slabs(lat, bounds, zchunk):
