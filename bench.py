@@ -55,7 +55,7 @@ def cpu_baseline(w, ic) -> dict:
     t0 = time.perf_counter()
     O.evolve(st, 1)
     per = time.perf_counter() - t0
-    n = max(1, min(12, int(15.0 / max(per, 1e-3))))
+    n = max(1, min(48, int(12.0 / max(per, 1e-3))))  # about 12 s of wall time
     log(f"cpu baseline: 1 step {per:.2f} s, timing {n} more")
     t0 = time.perf_counter()
     O.evolve(st, n)
