@@ -15,6 +15,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -60,9 +61,21 @@ def cpu_baseline(w, ic) -> dict:
     t0 = time.perf_counter()
     O.evolve(st, n)
     el = time.perf_counter() - t0
-    return {"value": w.sites * n / el / 1e9, "unit": "Gsite-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
+    out = {"value": w.sites * n / el / 1e9, "unit": "Gsite-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
+    # one more step on a single thread (the oracle's OpenMP loops, one thread)
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        O.evolve(st, 1)
+        el1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(cores)
+        out["single_thread"] = {"value": w.sites / el1 / 1e9, "sample": "1 leapfrog step, 1 thread"}
+    except OSError:
+        out["single_thread"] = None
+    return out
 
 
 def time_extras(w, dtype) -> tuple[dict, dict]:
@@ -155,6 +168,8 @@ def time_slab_share(lat, w, gpus: int = 8, reps: int = 20) -> dict:
 
 def time_additions() -> dict:
     """Measured numbers of the rows and additions beyond the step itself:
+    the 256^3 lambda phi^4 workload (its 1000 steps; a quarter of its working
+    set fits in the 256 MB MALL, so its rate is not a pure HBM figure),
     rho/p per site at 512^3 (algorithmic 16 B read + 8 B written per site,
     FP32 outputs), the ensemble of uneven lattices (500 steps), and the
     adjoint of the 128^3 workload (500 steps, checkpoints every 50)."""
@@ -164,6 +179,20 @@ def time_additions() -> dict:
     from paper_0911_5692_amd import workloads as W
 
     out = {}
+    w2 = W.CFG2
+    ic = W.make_inputs(w2)
+    lat = Lattice(**w2.model(), dtype=torch.float32, device="cuda:0")
+    lat.init_physical(*(torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+    lat.step(20)
+    torch.cuda.synchronize()
+    lat.step(w2.steps)
+    ms = lat.last_step_ms() / w2.steps
+    out["lphi4_256"] = {"N": w2.N, "steps": w2.steps, "ms_per_step": round(ms, 5),
+                        "Gsite_updates_per_s": round(w2.sites / ms / 1e6, 2),
+                        "hbm_frac_algorithmic": round(32 * w2.sites / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    lat.close()
+    del ic
+
     w = W.CFG3
     lat = Lattice(**w.model(), dtype=torch.float32, device="cuda:0", **W.BENCH_SHAPES[w.name])
     lat.init_vacuum(W.vacuum_spec(w, seed=w.cfg), 1.0)
