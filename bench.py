@@ -168,8 +168,8 @@ def time_slab_share(lat, w, gpus: int = 8, reps: int = 20) -> dict:
 
 def time_additions() -> dict:
     """Measured numbers of the rows and additions beyond the step itself:
-    the 256^3 lambda phi^4 workload (its 1000 steps; a quarter of its working
-    set fits in the 256 MB MALL, so its rate is not a pure HBM figure),
+    the 256^3 lambda phi^4 workload (its 1000 steps; its eight arrays, 512 MB,
+    are only twice the 256 MB MALL, so its rate is not a pure HBM figure),
     rho/p per site at 512^3 (algorithmic 16 B read + 8 B written per site,
     FP32 outputs), the ensemble of uneven lattices (500 steps), and the
     adjoint of the 128^3 workload (500 steps, checkpoints every 50)."""
