@@ -257,7 +257,8 @@ int lf_stream_copy(const float *a0, const float *a1, const float *a2, const floa
  * (bad arguments, nz outside [1, N], partials too small), LF_ESTATE (no step
  * since lf_init / lf_set_state), LF_EHIP.  Exchanging halos and summing the
  * partial rows across slabs (then the scale-factor update from the global
- * sums) is the multi-GPU driver's part and is not in this library. */
+ * sums) belongs to the multi-GPU program that calls this and is not in this
+ * library. */
 int lf_slab_rows(const lf_ctx *ctx, int nz, int zchunk, int64_t *rows);
 int lf_slab_sweep(lf_ctx *ctx, int nz, int zchunk, const void *const in[4], const void *const lo[4],
                   const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows);
