@@ -73,6 +73,15 @@ def test_cfg3_full_size_512_periodic_tiles():
     _check(W.CFG3.resized(64), W.CFG3.steps, reps=8, **W.BENCH_SHAPES[W.CFG3.name])
 
 
+@pytest.mark.parametrize("stencil", [7, 27])
+def test_large_1024_periodic_tiles(stencil):
+    """1024^3 FP32 (34 GB of lattice arrays, 8x the benchmark's sites) in the
+    automatic launch shape, 100 steps: every 64^3 periodic copy bitwise equal
+    and equal to the oracle's 64^3 run."""
+    from dataclasses import replace
+    _check(replace(W.CFG3, stencil=stencil).resized(64), 100, reps=16)
+
+
 @pytest.mark.parametrize("N", [4, 5, 7, 33, 100])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_edge_and_ragged_sizes(N, dtype):
