@@ -172,6 +172,19 @@ def test_step_before_init_is_a_state_error():
     assert ei.value.code == 1
 
 
+def test_zero_steps_leave_the_state_unchanged():
+    w = W.CFG1.resized(24)
+    _, _, _, ic = oracle_run(w, 5)
+    lat, _ = gpu_run(w, ic, 5)
+    arrays, sc = lat.get_state()
+    lat.step(0)
+    arrays2, sc2 = lat.get_state()
+    for a, b in zip(arrays, arrays2):
+        assert torch.equal(a, b)
+    assert sc2.step == sc.step == 5 and sc2.a_half == sc.a_half and sc2.ad == sc.ad
+    assert lat.energies()["step"] == 5
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_rho_p_matches_oracle(dtype, tol):
     """Per-site energy density and pressure (the paper's second kernel) and
