@@ -112,9 +112,19 @@ class Lattice:
     def __init__(self, N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float,
                  s: float, kappa2: float, dtype: torch.dtype = torch.float32,
                  device: str | torch.device = "cuda", tile_y: int = 0, zchunk: int = 0,
-                 tile_x: int = 0, stream: torch.cuda.Stream | None = None, stencil: int = 7):
+                 tile_x: int = 0, stream: torch.cuda.Stream | None = None, stencil: int = 7,
+                 tuned: bool | str = False):
+        """tuned: take the launch shape from the autotuner (its cache, or a
+        tuning run on a miss) when no tile_y / zchunk / tile_x is given; a
+        string is the cache path (default: LF_AUTOTUNE_CACHE or the package's
+        autotune_cache.jsonl)."""
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float32 or torch.float64")
+        if tuned and not (tile_y or zchunk or tile_x):
+            t = autotune(N, L, dt, beta, c1, G, r, s, kappa2, dtype=dtype, device=device,
+                         cache_path=tuned if isinstance(tuned, str) else DEFAULT_TUNE_CACHE, stencil=stencil)
+            tile_x, tile_y, zchunk = t["tile_x"], t["tile_y"], t["zchunk"]
+        self.launch_shape = dict(tile_x=int(tile_x), tile_y=int(tile_y), zchunk=int(zchunk))
         self.N, self.dtype = int(N), dtype
         self.device = torch.device(device)
         self.params = Params(int(N), _DT[dtype], float(L), float(dt), int(beta), 0, float(c1),
