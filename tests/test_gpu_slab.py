@@ -77,6 +77,9 @@ CASES = [
     (27, CFG3_48, F32, dict(tile_x=128, tile_y=8), [0, 1, 2, 25, 48], 0),
     (7, W.CFG1.resized(40), F64, dict(tile_x=64, tile_y=4), [0, 13, 14, 40], 5),
     (27, W.CFG1.resized(40), F64, dict(tile_x=64, tile_y=16), [0, 13, 14, 40], 0),
+    # one slab holding the whole lattice: every halo plane is one of its own
+    (7, W.CFG1.resized(48), F32, dict(tile_x=64, tile_y=8), [0, 48], 0),
+    (27, W.CFG1.resized(48), F32, dict(tile_x=64, tile_y=8), [0, 48], 16),
     # 128-wide tiles in FP64 (a tile wider than the lattice: ragged in x)
     (7, W.CFG1.resized(40), F64, dict(tile_x=128, tile_y=4), [0, 7, 40], 6),
     (27, W.CFG1.resized(40), F64, dict(tile_x=128, tile_y=8), [0, 7, 40], 0),
