@@ -48,6 +48,18 @@ def measured_traffic(workload: str, stencil: int, shape: dict):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, ic) -> dict:
     import oracle as O
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
@@ -62,7 +74,8 @@ def cpu_baseline(w, ic) -> dict:
     O.evolve(st, n)
     el = time.perf_counter() - t0
     out = {"value": w.sites * n / el / 1e9, "unit": "Gsite-updates/s", "cores": cores,
-           "kind": "oracle",
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "precision": f"FP64 oracle (the GPU path computes in {w.dtype.upper()})",
            "sample": f"{n} leapfrog steps of the {w.N}^3 workload, FP64 C oracle, OpenMP {cores} threads"}
     # one more step on a single thread (the oracle's OpenMP loops, one thread)
     try:
@@ -328,7 +341,14 @@ def main() -> int:
     ad0 = lat.init_physical(*dev, ic["a0"])
     del dev
     torch.cuda.synchronize()
-    log(f"initialised, a'(0) = {ad0:.6f}; warmup {args.warmup} steps")
+    # The per-kernel timing (eager steps with HIP events around each kernel)
+    # runs before the timed region.  After the device has idled (input
+    # generation, upload), its first milliseconds of work run about 10%
+    # slower while the clocks come up; this leg does that, so that a short
+    # timed run sees the rate of a long one.
+    log(f"initialised, a'(0) = {ad0:.6f}; timing each kernel over {args.kernel_steps} eager steps")
+    kms = lat.time_kernels(args.kernel_steps)
+    log(f"warmup {args.warmup} steps")
     lat.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -346,7 +366,6 @@ def main() -> int:
     en = lat.energies()
     log(f"energies after {en['step']} steps: a={en['a']:.6f} R={en['R']:.3e}")
 
-    kms = lat.time_kernels(args.kernel_steps)
     sweep_ms = kms[1]
     alg_bytes = 8 * esize * w.sites  # read f, v; write v, f_new; two fields
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9

@@ -35,6 +35,7 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxLogK = 5;          // longest step graph: 32 steps
 constexpr int kRedBlocks = 2048;     // grid of the grid-stride reductions
 
 // Sweep variant and launch shape.  tile_y: 1 = plain one-site-per-thread
@@ -195,9 +196,13 @@ struct lf_ctx {
     DevScalars *S;
     CoefPair *C;
     int inited;
-    hipGraphExec_t g1[2];
-    hipGraphExec_t gK[2];
-    int K;
+    // g[j][p]: 2^j steps from buffer parity p, j = 0 .. logK (K = 2^logK
+    // steps per long graph).  An n-step call launches n div K long graphs and
+    // one graph per set bit of n mod K.
+    hipGraphExec_t g[kMaxLogK + 1][2];
+    int logK;
+    int graphs_ready;   // every g[j][p] instantiated and uploaded
+    int ens_member;     // stepped by an ensemble: its own graphs are never used
     hipEvent_t ev0, ev1;
     int timed;
     int64_t hstep;  // steps since lf_init / lf_set_state, as enqueued by the host
@@ -267,6 +272,29 @@ int capture(lf_ctx *c, int nsteps, int start, hipGraphExec_t *exec)
     hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e3 != hipSuccess) return fail(LF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    return LF_OK;
+}
+
+// The graph of 2^j steps from parity p, captured on first use.
+int ensure_graph(lf_ctx *c, int j, int p)
+{
+    if (c->g[j][p]) return LF_OK;
+    return capture(c, 1 << j, p, &c->g[j][p]);
+}
+
+// Instantiate and upload every graph lf_step can launch, so that no call
+// pays for a capture or for a graph's first upload.  Runs at lf_init /
+// lf_set_state, once per context (the graphs depend only on the buffers).
+int prepare_graphs(lf_ctx *c)
+{
+    if (c->graphs_ready || c->ens_member) return LF_OK;
+    int rc;
+    for (int j = 0; j <= c->logK; ++j)
+        for (int p = 0; p < 2; ++p) {
+            if ((rc = ensure_graph(c, j, p))) return rc;
+            HIPCHK(hipGraphUpload(c->g[j][p], c->stream));
+        }
+    c->graphs_ready = 1;
     return LF_OK;
 }
 
@@ -341,7 +369,7 @@ int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes
     c->P = (DevParams *)(c->ws + L.P);
     c->S = (DevScalars *)(c->ws + L.S);
     c->C = (CoefPair *)(c->ws + L.C);
-    c->K = (p->N >= 256) ? 8 : 32;
+    c->logK = (p->N >= 256) ? 3 : 5;
     hipError_t e;
     DevParams dp;
     fill_dev_params(p, &dp);
@@ -358,10 +386,9 @@ int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes
 int lf_destroy(lf_ctx *c)
 {
     if (!c) return LF_OK;
-    for (int b = 0; b < 2; ++b) {
-        if (c->g1[b]) (void)hipGraphExecDestroy(c->g1[b]);
-        if (c->gK[b]) (void)hipGraphExecDestroy(c->gK[b]);
-    }
+    for (int j = 0; j <= kMaxLogK; ++j)
+        for (int b = 0; b < 2; ++b)
+            if (c->g[j][b]) (void)hipGraphExecDestroy(c->g[j][b]);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -393,7 +420,7 @@ static int init_common(lf_ctx *c, const void *f1, const void *f2, const void *v1
     c->timed = 0;
     c->hstep = 0;
     c->adj_ready = 0;
-    return LF_OK;
+    return prepare_graphs(c);
 }
 
 int lf_init(lf_ctx *c, const void *f1, const void *f2, const void *v1, const void *v2, int in_dtype,
@@ -422,21 +449,23 @@ int lf_step(lf_ctx *c, int64_t n)
     if (n < 0) return fail(LF_EINVAL, "n=%lld < 0", (long long)n);
     if (!c->inited) return fail(LF_ESTATE, "lf_step before lf_init");
     if (n == 0) return LF_OK;
-    const int64_t n0 = n;
+    const int64_t n0 = n, K = (int64_t)1 << c->logK;
     int rc;
-    if (n >= c->K && !c->gK[c->cur] && (rc = capture(c, c->K, c->cur, &c->gK[c->cur]))) return rc;
+    // every graph this call launches exists before the first event
+    if (n >= K && (rc = ensure_graph(c, c->logK, c->cur))) return rc;
+    for (int j = c->logK - 1, p = c->cur; j >= 0; --j)
+        if (n % K & ((int64_t)1 << j)) {
+            if ((rc = ensure_graph(c, j, p))) return rc;
+            if (j == 0) p ^= 1;
+        }
     if ((rc = ensure_events(&c->ev0, &c->ev1))) return rc;
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    while (n >= c->K) {
-        HIPCHK(hipGraphLaunch(c->gK[c->cur], c->stream));
-        n -= c->K;
-    }
-    while (n > 0) {
-        if (!c->g1[c->cur] && (rc = capture(c, 1, c->cur, &c->g1[c->cur]))) return rc;
-        HIPCHK(hipGraphLaunch(c->g1[c->cur], c->stream));
-        c->cur ^= 1;
-        --n;
-    }
+    for (; n >= K; n -= K) HIPCHK(hipGraphLaunch(c->g[c->logK][c->cur], c->stream));
+    for (int j = c->logK - 1; j >= 0; --j)
+        if (n & ((int64_t)1 << j)) {
+            HIPCHK(hipGraphLaunch(c->g[j][c->cur], c->stream));
+            if (j == 0) c->cur ^= 1;  // an odd step count swaps the buffers
+        }
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = 1;
     c->hstep += n0;
@@ -579,7 +608,7 @@ int lf_set_state(lf_ctx *c, const void *d1, const void *d2, const void *e1, cons
     c->inited = 1;
     c->hstep = s->step;
     c->adj_ready = 0;
-    return LF_OK;
+    return prepare_graphs(c);
 }
 
 int lf_set_coupling(lf_ctx *c, double G)
@@ -1291,6 +1320,10 @@ size_t ens_layout(int R, const lf_params *per, size_t *sub_off, int *nitems)
 
 }  // namespace
 
+namespace {
+int ens_prepare_graphs(lf_ens *e);
+}
+
 extern "C" {
 
 int lf_ens_workspace_bytes(int R, const lf_params *per, size_t *out_bytes)
@@ -1362,6 +1395,7 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
         rc = lf_create(&q, stream, ws + so[r], so[r + 1] - so[r], &e->sub[r]);
         if (rc) break;
         lf_ctx *c = e->sub[r];
+        c->ens_member = 1;
         EnsEntry &t = htab[r];
         memset(&t, 0, sizeof t);
         for (int b = 0; b < 2; ++b)
@@ -1400,6 +1434,10 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     const lf_params q0 = ens_sub_params(&per[0], &per[0], false);
     int res = resident_blocks(&q0, e->tile_x, e->tile_y);
     e->grid = nitems < res ? nitems : res;
+    if ((rc = ens_prepare_graphs(e))) {
+        lf_ens_destroy(e);
+        return rc;
+    }
     *out = e;
     return LF_OK;
 }
@@ -1432,6 +1470,20 @@ int ens_capture(lf_ens *e, int nsteps, int start, hipGraphExec_t *exec)
     hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e3 != hipSuccess) return fail(LF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    return LF_OK;
+}
+
+// Instantiate and upload the ensemble's step graphs (two steps from parity
+// 0, one step from either parity) at create, outside any timed call.
+int ens_prepare_graphs(lf_ens *e)
+{
+    int rc;
+    if ((rc = ens_capture(e, 2, 0, &e->g2))) return rc;
+    HIPCHK(hipGraphUpload(e->g2, e->stream));
+    for (int p = 0; p < 2; ++p) {
+        if ((rc = ens_capture(e, 1, p, &e->g1[p]))) return rc;
+        HIPCHK(hipGraphUpload(e->g1[p], e->stream));
+    }
     return LF_OK;
 }
 

@@ -1,0 +1,77 @@
+"""Write the stored oracle result of the 512^3 m^2 phi^2 workload.
+
+The workload is the chaotic-inflation model of Sec. III in program units
+(V_pr = f1^2/2 + G a^-3 f1^2 f2^2/2, G = 2.5e5, r = 3/2, s = 0) on a 512^3
+periodic lattice with L = 10, dt = 2^-10 and the seeded vacuum initial state
+(seeds [3, 0, field, kind]), evolved 2000 leapfrog steps with the 7-point
+Laplacian (eq. evo, eq. scalar-evo, eq. scale).
+
+The FP64 oracle runs the whole lattice; the file keeps
+  * the [0, 64)^3 corner of f1(k+1/2), f2(k+1/2), v1(k), v2(k) at k = 2000:
+    its sites reach across the periodic wrap in x, y and z within the
+    lattice's light cone (2000 steps at dt/dx = 1/20 is 100 sites);
+  * the four arrays at 16384 sites drawn uniformly over the whole lattice
+    (generator seed 2000, stored with their flat indices (z N + y) N + x);
+  * the whole-lattice means of the four arrays, the scale factor a_{k+1/2},
+    a'_k, a'_0 and the synchronised energies.
+
+Only the oracle and the seeded input generator are called.  About an hour on
+8 host cores.  Usage: python tests/golden/make_cfg3_512_crop.py
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from paper_0911_5692_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(HERE, "cfg3_512_crop.npz")
+CROP = 64
+NSAMPLE = 16384
+SAMPLE_SEED = 2000
+
+
+def main() -> int:
+    w = W.CFG3
+    t0 = time.time()
+    ic = W.make_inputs(w)
+    m = O.Model(**w.model())
+    v1, v2, ad0 = O.init_physical(m, ic["f1"], ic["f2"], ic["u1"], ic["u2"], ic["a0"])
+    st = O.start(m, ic["f1"], ic["f2"], v1, v2, ic["a0"], ad0)
+    del ic, v1, v2
+    print(f"initialised in {time.time() - t0:.0f} s, a'(0) = {ad0!r}", flush=True)
+    done = 0
+    while done < w.steps:
+        n = min(100, w.steps - done)
+        O.evolve(st, n)
+        done += n
+        print(f"{done} steps, {time.time() - t0:.0f} s", flush=True)
+    en = O.energies(st)
+    rng = np.random.default_rng(SAMPLE_SEED)
+    idx = np.sort(rng.choice(w.sites, size=NSAMPLE, replace=False)).astype(np.int64)
+    arrays = {k: getattr(st, k) for k in ("f1", "f2", "v1", "v2")}
+    out = dict(
+        N=np.int64(w.N), steps=np.int64(w.steps), crop=np.int64(CROP), ad0=np.float64(ad0),
+        a_half=np.float64(st.a_half), ad=np.float64(st.ad),
+        energy_keys=np.array(O.ENERGY_KEYS), energies=np.array([en[k] for k in O.ENERGY_KEYS]),
+        sample_index=idx,
+    )
+    for k, a in arrays.items():
+        out[f"crop_{k}"] = np.ascontiguousarray(a[:CROP, :CROP, :CROP])
+        out[f"sample_{k}"] = a.reshape(-1)[idx].copy()
+        out[f"mean_{k}"] = np.float64(a.mean())
+    np.savez_compressed(OUT, **out)
+    print(f"wrote {OUT} in {time.time() - t0:.0f} s: energies {en}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,90 @@
+"""Full-size parity on the workloads' own seeded inputs (no periodic tiling).
+
+* The 256^3 lambda phi^4 workload (Gaussian random fields, 1000 steps, FP32,
+  automatic launch shape) against the FP64 oracle run here, element by
+  element over the whole lattice.
+* The 512^3 m^2 phi^2 workload (vacuum fluctuations, 2000 steps, FP32, the
+  benchmark's launch shape: 128 x 8 tiles, two 256-plane z-chunks) against
+  the stored FP64 oracle result (tests/golden/cfg3_512_crop.npz, written by
+  tests/golden/make_cfg3_512_crop.py): the [0, 64)^3 corner, 16384 sites
+  drawn over the whole lattice, the scale factor, a', the Friedmann residual
+  and the energies.
+
+Per array the error is bounded both against max|oracle| and against the
+oracle's fluctuation max|oracle - <oracle>| (the inflaton is 1 + O(1e-4)).
+Unlike the periodic-tiling tests, these see index and wrap errors that are a
+multiple of 64 sites and errors at the z-chunk boundary.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from _parity import ARRAYS, compare_state, fluct_err, gpu_run, log, oracle_run, rel_err
+from paper_0911_5692_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CFG3_FIXTURE = os.path.join(HERE, "golden", "cfg3_512_crop.npz")
+TOL = 1e-5
+
+
+def _check_scalars(g, en):
+    assert abs(g["a"] - en["a"]) <= 1e-9 * en["a"]
+    assert abs(g["ad"] - en["ad"]) <= 1e-9 * abs(en["ad"])
+    assert abs(g["R"] - en["R"]) <= 1e-8
+    for k in ("K1", "K2", "G1", "G2", "P", "rho"):
+        assert abs(g[k] - en[k]) <= TOL * abs(en[k]), k
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_256_own_inputs_1000_steps():
+    w = W.CFG2
+    log(f"[fullsize] {w.name} N={w.N} steps={w.steps}: oracle")
+    st, en, ad0, ic = oracle_run(w, w.steps)
+    log("[fullsize] oracle done; GPU run (automatic launch shape)")
+    lat, gad0 = gpu_run(w, ic, w.steps)
+    assert abs(gad0 - ad0) <= 1e-12 * ad0
+    f = [x.cpu().numpy() for x in lat.fields(dtype=torch.float64)]
+    errs = compare_state(f, st)
+    g = lat.energies()
+    log(f"[fullsize] {w.name}: {errs} a {g['a']} vs {en['a']} R {g['R']} vs {en['R']}")
+    for k in ARRAYS:
+        assert errs[k] <= TOL, (k, errs)
+    _check_scalars(g, en)
+    assert g["step"] == w.steps
+    lat.close()
+
+
+@pytest.mark.timeout(900)
+def test_cfg3_512_own_inputs_2000_steps_vs_stored_oracle():
+    if not os.path.exists(CFG3_FIXTURE):
+        pytest.fail(f"missing {CFG3_FIXTURE}: run tests/golden/make_cfg3_512_crop.py")
+    ref = np.load(CFG3_FIXTURE, allow_pickle=False)
+    w = W.CFG3
+    assert int(ref["N"]) == w.N and int(ref["steps"]) == w.steps
+    c = int(ref["crop"])
+    log(f"[fullsize] {w.name} N={w.N} steps={w.steps} shape={W.BENCH_SHAPES[w.name]}: host inputs")
+    ic = W.make_inputs(w)
+    log("[fullsize] GPU run")
+    lat, gad0 = gpu_run(w, ic, w.steps, **W.BENCH_SHAPES[w.name])
+    del ic
+    assert abs(gad0 - float(ref["ad0"])) <= 1e-12 * float(ref["ad0"])
+    idx = torch.from_numpy(ref["sample_index"]).to("cuda")
+    errs = {}
+    for k, x in zip(ARRAYS, lat.fields(dtype=torch.float64)):
+        crop = x[:c, :c, :c].cpu().numpy()
+        samp = x.reshape(-1)[idx].cpu().numpy()
+        rc, rs = ref[f"crop_{k}"], ref[f"sample_{k}"]
+        errs[k] = dict(crop=max(rel_err(crop, rc), fluct_err(crop, rc)),
+                       sample=max(rel_err(samp, rs), fluct_err(samp, rs)))
+    g = lat.energies()
+    en = dict(zip([str(s) for s in ref["energy_keys"]], (float(v) for v in ref["energies"])))
+    log(f"[fullsize] {w.name}: {errs} a {g['a']} vs {en['a']} R {g['R']} vs {en['R']}")
+    for k in ARRAYS:
+        assert errs[k]["crop"] <= TOL and errs[k]["sample"] <= TOL, (k, errs)
+    _check_scalars(g, en)
+    assert g["step"] == w.steps
+    lat.close()
