@@ -263,6 +263,26 @@ int lf_slab_rows(const lf_ctx *ctx, int nz, int zchunk, int64_t *rows);
 int lf_slab_sweep(lf_ctx *ctx, int nz, int zchunk, const void *const in[4], const void *const lo[4],
                   const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows);
 
+/* Allocation-free variant of lf_slab_sweep, for callers that cannot allocate
+ * device memory around the call (code under HIP graph capture, tight
+ * stepping loops, harnesses that forbid hipMalloc).  The same sweep with the
+ * same arguments and outputs `out`, except that the partial-sum rows go to a
+ * static device array the library holds on each GPU (65536 rows of 4
+ * doubles, 2 MiB, kept until the process ends) and are added, in the fixed
+ * order of the scale-factor update, into sums[0..3] (a caller-owned device
+ * array of 4 doubles, 8-byte aligned): the slab's totals of the two gradient
+ * energies, f1^beta and f1^2 f2^2 of the new fields, which the multi-GPU
+ * program adds across slabs.  The call allocates nothing and calls no
+ * allocating library routine.  Nothing in the array has to start at zero:
+ * each call's sweep writes every row it sums.  All calls on one GPU share
+ * its array, so calls that overlap in time on one GPU (other streams, other
+ * threads, other contexts) race and give undefined sums; serialise them.
+ * Asynchronous on the context's stream.  Errors: as lf_slab_sweep, and
+ * LF_EINVAL when the launch shape needs more than 65536 rows (a larger
+ * zchunk, or lf_slab_sweep with a caller buffer, avoids that). */
+int lf_slab_sweep_sums(lf_ctx *ctx, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                       const void *const hi[2], void *const out[4], double *sums);
+
 /* ---- autotuner ---------------------------------------------------------- */
 
 /* Workspace for lf_autotune with these parameters (largest candidate). */

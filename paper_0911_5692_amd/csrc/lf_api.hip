@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 using namespace lf;
@@ -188,6 +189,7 @@ struct lf_ctx {
     Shape sh;
     hipStream_t stream;
     hipStream_t cap;
+    int device;         // current device at lf_create (the stream's device)
     char *ws;
     void *buf[2][4];
     int cur;
@@ -325,6 +327,40 @@ int check_ptr(const void *ptr, const char *name)
     return LF_OK;
 }
 
+// Allocation-free slab sweep (lf_slab_sweep_sums): the partial-sum rows of
+// one call live in this array, which the library holds on every GPU it runs
+// on until the process ends (kScratchRows rows of kNPart doubles, 2 MiB).
+// Host code never passes the array's name to a kernel or a copy: on the host
+// it is only a stand-in for the symbol.  Its device address is looked up once
+// per device (scratch_rows) and that address is what the kernels receive.
+constexpr int kScratchRows = 65536;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchRows * kNPart];
+
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on device dev (looked up with dev current on
+// the first call for that device, then kept).
+int scratch_rows(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LF_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int prev = 0;
+        HIPCHK(hipGetDevice(&prev));
+        if (prev != dev) HIPCHK(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != dev) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !ptr)
+            return fail(LF_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return LF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -358,6 +394,10 @@ int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes
     c->L = L;
     c->sh = shape_of(p);
     c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(LF_EHIP, "hipGetDevice failed");
+    }
     c->ws = (char *)workspace;
     for (int b = 0; b < 2; ++b)
         for (int j = 0; j < 4; ++j) c->buf[b][j] = c->ws + L.state[b][j];
@@ -661,8 +701,8 @@ int lf_slab_rows(const lf_ctx *c, int nz, int zchunk, int64_t *rows)
     return slab_shape(c, nz, zchunk, &z, rows);
 }
 
-int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
-                  const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows)
+static int slab_sweep_impl(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                           const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows)
 {
     int z;
     int64_t rows;
@@ -721,6 +761,36 @@ int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const 
     io.nz = nz;
     launch_sweep_slab(stencil_of(&c->p), c->p.dtype, c->sh.tile_x, c->sh.tile_y, c->p.beta, io, c->p.N, z,
                       c->C, partials, c->stream);
+    HIPCHK(hipGetLastError());
+    return LF_OK;
+}
+
+int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                  const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows)
+{
+    return slab_sweep_impl(c, nz, zchunk, in, lo, hi, out, partials, partial_rows);
+}
+
+int lf_slab_sweep_sums(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
+                       const void *const hi[2], void *const out[4], double *sums)
+{
+    int z;
+    int64_t rows;
+    int rc = slab_shape(c, nz, zchunk, &z, &rows);
+    if (rc) return rc;
+    if (!sums) return fail(LF_EINVAL, "sums is NULL");
+    if ((uintptr_t)sums % sizeof(double)) return fail(LF_EINVAL, "sums is not 8-byte aligned");
+    if (rows > kScratchRows)
+        return fail(LF_EINVAL,
+                    "the sweep writes %lld partial rows, the library's static scratch holds %d: use a larger "
+                    "zchunk, or lf_slab_sweep with a caller buffer",
+                    (long long)rows, kScratchRows);
+    double *rows_dev = nullptr;
+    if ((rc = scratch_rows(c->device, &rows_dev))) return rc;
+    if ((rc = slab_sweep_impl(c, nz, zchunk, in, lo, hi, out, rows_dev, kScratchRows))) return rc;
+    // every row the sweep's blocks write is read, in the fixed order of the
+    // scale-factor kernel's stage 2; rows beyond them are not read
+    launch_sum_partials(rows_dev, (int)rows, kNPart, sums, c->stream);
     HIPCHK(hipGetLastError());
     return LF_OK;
 }

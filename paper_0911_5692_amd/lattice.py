@@ -325,6 +325,27 @@ class Lattice:
         self._keep = (slab, lo, hi, out, part)
         return out, part
 
+    def slab_sweep_sums(self, slab, lo, hi, out, sums, zchunk: int = 0):
+        """The sweep of slab_sweep without a partial-row buffer
+        (lf_slab_sweep_sums): the rows go to the library's static device
+        array and their totals into `sums` (float64 tensor of 4 on the
+        device).  `out` and `sums` are the caller's; nothing is allocated.
+        Asynchronous on the lattice's stream."""
+        N, dt, dev = self.N, self.dtype, self.ws.device
+        nz = int(slab[0].shape[0])
+        want = [(nz, N, N)] * 4
+        lo_shapes = [(2, N, N), (2, N, N), (1, N, N), (1, N, N)]
+        for t, shp in zip((*slab, *lo, *hi, *out), want + lo_shapes + [(1, N, N)] * 2 + want):
+            if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
+                raise ValueError(f"slab arrays: contiguous {dt} tensors of shape {shp} on {dev}")
+        if tuple(sums.shape) != (4,) or sums.dtype != torch.float64 or sums.device != dev:
+            raise ValueError(f"sums: float64 tensor of shape (4,) on {dev}")
+        arr = lambda ts: (ctypes.c_void_p * len(ts))(*(t.data_ptr() for t in ts))
+        check(lib().lf_slab_sweep_sums(self._ctx, nz, int(zchunk), arr(slab), arr(lo), arr(hi), arr(out),
+                                       ctypes.c_void_p(sums.data_ptr())))
+        self._keep = (slab, lo, hi, out, sums)
+        return out, sums
+
     # ------------------------------------------------------------ adjoint
     def adjoint_forward(self, n: int, K: int, weights=(0.0, 1.0, 0.0, 1.0)) -> float:
         """Run n steps with checkpoints every K steps; returns the loss
