@@ -39,18 +39,19 @@ NSAMPLE = 16384
 SAMPLE_SEED = 2000
 
 
-def main() -> int:
-    w = W.CFG3
+def run(w, steps: int, out_path: str) -> dict:
+    """Evolve workload w for `steps` steps with the oracle from its seeded
+    inputs and store the corner crop, the random sample and the scalars."""
     t0 = time.time()
     ic = W.make_inputs(w)
     m = O.Model(**w.model())
     v1, v2, ad0 = O.init_physical(m, ic["f1"], ic["f2"], ic["u1"], ic["u2"], ic["a0"])
     st = O.start(m, ic["f1"], ic["f2"], v1, v2, ic["a0"], ad0)
     del ic, v1, v2
-    print(f"initialised in {time.time() - t0:.0f} s, a'(0) = {ad0!r}", flush=True)
+    print(f"{w.name}: initialised in {time.time() - t0:.0f} s, a'(0) = {ad0!r}", flush=True)
     done = 0
-    while done < w.steps:
-        n = min(100, w.steps - done)
+    while done < steps:
+        n = min(100, steps - done)
         O.evolve(st, n)
         done += n
         print(f"{done} steps, {time.time() - t0:.0f} s", flush=True)
@@ -59,8 +60,8 @@ def main() -> int:
     idx = np.sort(rng.choice(w.sites, size=NSAMPLE, replace=False)).astype(np.int64)
     arrays = {k: getattr(st, k) for k in ("f1", "f2", "v1", "v2")}
     out = dict(
-        N=np.int64(w.N), steps=np.int64(w.steps), crop=np.int64(CROP), ad0=np.float64(ad0),
-        a_half=np.float64(st.a_half), ad=np.float64(st.ad),
+        N=np.int64(w.N), steps=np.int64(steps), stencil=np.int64(w.stencil), crop=np.int64(CROP),
+        ad0=np.float64(ad0), a_half=np.float64(st.a_half), ad=np.float64(st.ad),
         energy_keys=np.array(O.ENERGY_KEYS), energies=np.array([en[k] for k in O.ENERGY_KEYS]),
         sample_index=idx,
     )
@@ -68,8 +69,13 @@ def main() -> int:
         out[f"crop_{k}"] = np.ascontiguousarray(a[:CROP, :CROP, :CROP])
         out[f"sample_{k}"] = a.reshape(-1)[idx].copy()
         out[f"mean_{k}"] = np.float64(a.mean())
-    np.savez_compressed(OUT, **out)
-    print(f"wrote {OUT} in {time.time() - t0:.0f} s: energies {en}", flush=True)
+    np.savez_compressed(out_path, **out)
+    print(f"wrote {out_path} in {time.time() - t0:.0f} s: energies {en}", flush=True)
+    return en
+
+
+def main() -> int:
+    run(W.CFG3, W.CFG3.steps, OUT)
     return 0
 
 

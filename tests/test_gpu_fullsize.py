@@ -4,11 +4,12 @@
   automatic launch shape) against the FP64 oracle run here, element by
   element over the whole lattice.
 * The 512^3 m^2 phi^2 workload (vacuum fluctuations, 2000 steps, FP32, the
-  benchmark's launch shape: 128 x 8 tiles, two 256-plane z-chunks) against
-  the stored FP64 oracle result (tests/golden/cfg3_512_crop.npz, written by
-  tests/golden/make_cfg3_512_crop.py): the [0, 64)^3 corner, 16384 sites
-  drawn over the whole lattice, the scale factor, a', the Friedmann residual
-  and the energies.
+  benchmark's launch shape: 128 x 8 tiles, two 256-plane z-chunks) and the
+  256^3 configuration the paper times with its 27-point Laplacian (600
+  steps, 128 x 8 tiles, 32-plane z-chunks) against stored FP64 oracle
+  results (tests/golden/*_crop.npz, written by tests/golden/make_*_crop.py):
+  the [0, 64)^3 corner, 16384 sites drawn over the whole lattice, the scale
+  factor, a', the Friedmann residual and the energies.
 
 Per array the error is bounded both against max|oracle| and against the
 oracle's fluctuation max|oracle - <oracle>| (the inflaton is 1 + O(1e-4)).
@@ -27,7 +28,6 @@ from paper_0911_5692_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CFG3_FIXTURE = os.path.join(HERE, "golden", "cfg3_512_crop.npz")
 TOL = 1e-5
 
 
@@ -58,18 +58,32 @@ def test_cfg2_256_own_inputs_1000_steps():
     lat.close()
 
 
+STORED = [
+    # workload, stored oracle result (tests/golden/make_*_crop.py), launch shape
+    (W.CFG3, "cfg3_512_crop.npz"),
+    (W.PAPER_256_S27, "paper256_s27_crop.npz"),
+]
+
+
 @pytest.mark.timeout(900)
-def test_cfg3_512_own_inputs_2000_steps_vs_stored_oracle():
-    if not os.path.exists(CFG3_FIXTURE):
-        pytest.fail(f"missing {CFG3_FIXTURE}: run tests/golden/make_cfg3_512_crop.py")
-    ref = np.load(CFG3_FIXTURE, allow_pickle=False)
-    w = W.CFG3
-    assert int(ref["N"]) == w.N and int(ref["steps"]) == w.steps
+@pytest.mark.parametrize("w,fixture", STORED, ids=[w.name for w, _ in STORED])
+def test_own_inputs_vs_stored_oracle(w, fixture):
+    """The benchmark's 512^3 workload (7-point, 2000 steps, 128 x 8 tiles with
+    two 256-plane z-chunks) and the paper's timed 256^3 configuration
+    (27-point, 600 steps, 128 x 8 tiles with 32-plane z-chunks), each from
+    its own seeded vacuum inputs, against the stored FP64 oracle result."""
+    path = os.path.join(HERE, "golden", fixture)
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run the tests/golden/make_*_crop.py script that writes it")
+    ref = np.load(path, allow_pickle=False)
+    steps = int(ref["steps"])
+    assert int(ref["N"]) == w.N
     c = int(ref["crop"])
-    log(f"[fullsize] {w.name} N={w.N} steps={w.steps} shape={W.BENCH_SHAPES[w.name]}: host inputs")
+    shape = W.BENCH_SHAPES[w.name]
+    log(f"[fullsize] {w.name} N={w.N} stencil={w.stencil} steps={steps} shape={shape}: host inputs")
     ic = W.make_inputs(w)
     log("[fullsize] GPU run")
-    lat, gad0 = gpu_run(w, ic, w.steps, **W.BENCH_SHAPES[w.name])
+    lat, gad0 = gpu_run(w, ic, steps, **shape)
     del ic
     assert abs(gad0 - float(ref["ad0"])) <= 1e-12 * float(ref["ad0"])
     idx = torch.from_numpy(ref["sample_index"]).to("cuda")
@@ -86,5 +100,5 @@ def test_cfg3_512_own_inputs_2000_steps_vs_stored_oracle():
     for k in ARRAYS:
         assert errs[k]["crop"] <= TOL and errs[k]["sample"] <= TOL, (k, errs)
     _check_scalars(g, en)
-    assert g["step"] == w.steps
+    assert g["step"] == steps
     lat.close()
