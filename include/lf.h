@@ -96,8 +96,8 @@ typedef struct lf_params {
                          128-wide tiles, else as many as fit, with chunks of at most
                          64 planes) */
     int32_t tile_x;   /* sweep tile columns: 0 = automatic (128 x 8 from N = 256 up,
-                         64 x 8 or 64 x 4 below), 64 or 128 (128 with tile_y 4 or 8
-                         only) */
+                         64 x 8 or 64 x 4 below), 32, 64 or 128 (128 with tile_y 4 or
+                         8 only; 32 with tile_y 8 or 16 and the 7-point stencil only) */
     int32_t stencil;  /* Laplacian: 0 or 7 = 7-point, 27 = 27-point (see above) */
 } lf_params;
 
@@ -291,7 +291,8 @@ int lf_autotune_workspace_bytes(const lf_params *p, size_t *out_bytes);
  * dtype, beta and stencil on the current device.  If cache_path (may be
  * NULL) holds a line for (device architecture, N, dtype, beta, stencil), that
  * choice is returned (*best_ms = -1).  Otherwise every candidate (the plain
- * sweep; LDS tiles 64x4, 64x8, 64x16, 128x4, 128x8; z-chunks from the
+ * sweep; LDS tiles 64x4, 64x8, 64x16, 128x4, 128x8, and for the 7-point
+ * stencil 32x8, 32x16; z-chunks from the
  * automatic rule, 16, 32, 64, 128, N/6, N/4, N/3, N/2) is timed with HIP
  * events over graph-replayed steps
  * of a synthetic state, the fastest is returned in *best (p with the shape
@@ -331,12 +332,13 @@ int lf_adj_backward(lf_ctx *ctx, double dL, double *dL_dG, void *g_f1, void *g_f
  * Every step is two launches for the whole ensemble, captured in a HIP
  * graph: a batched FP64 scale-factor update (one block per realization, each
  * with its own a(t), background and averages) and one persistent sweep whose
- * grid walks a static list of (realization, tile, z-chunk) work items.  The
- * sweep tile is per_real[0].tile_x/tile_y (default 64 x 8) for all
+ * blocks take (realization, tile, z-chunk) work items from a device-wide
+ * counter, longest item first.  The sweep tile is per_real[0].tile_x/tile_y
+ * (default 64 x 8; 32-wide tiles for the 7-point stencil only) for all
  * realizations; z-chunks may differ per realization (default: the whole
  * lattice when the realizations' tile columns fill between half and all of
- * the resident grid, else N/2 planes, at least 8, or N when N < 8).  Work
- * items run longest chunk first.  Each realization's state matches a single-lattice run
+ * the resident grid, else N/2 planes, at least 8, or N when N < 8);
+ * lf_ens_autotune picks both by measurement.  Each realization's state matches a single-lattice run
  * with the same parameters to rounding. */
 int lf_ens_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
 int lf_ens_create(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,
@@ -356,6 +358,26 @@ int lf_ens_last_step_ms(lf_ens *ens, double *ms);
 int lf_ens_energies(lf_ens *ens, lf_report *out);
 int lf_ens_get_fields(lf_ens *ens, int r, void *f1, void *f2, void *v1, void *v2, int out_dtype,
                       int synchronized);
+
+/* Ensemble launch-shape autotuner (the block-size search of Sec. III, done
+ * by measurement).  Times the ensemble sweep of these realizations (sizes,
+ * dtype, beta and stencil as in per[]) for every candidate: each LDS tile
+ * (32 x 8 and 32 x 16 for the 7-point stencil, 64 x 4/8/16, 128 x 4/8) with
+ * z-chunks of target length 16 ... 192 planes, whole lattices, or the default
+ * rule (*ztarget = 0), on synthetic states in the caller's workspace
+ * (lf_ens_autotune_workspace_bytes), with HIP events over graph-replayed
+ * steps.  Returns the fastest tile and target; a realization's z-chunk for a
+ * target is lf_ens_zchunk(N, target).  If cache_path (may be NULL) holds a
+ * line for (device architecture, the multiset of sizes, dtype, beta,
+ * stencil), that choice is returned without timing (*best_ms = -1);
+ * otherwise the winner is appended as one JSON object per line.  Blocking. */
+int lf_ens_autotune_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
+int lf_ens_autotune(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,
+                    const char *cache_path, int *tile_x, int *tile_y, int *ztarget, double *best_ms);
+/* z-chunk of an N^3 realization for a target item length: the fewest equal
+ * chunks of at most `target` planes, i.e. ceil(N / ceil(N / target)); N when
+ * target >= N; 0 (the default rule) when target <= 0. */
+int lf_ens_zchunk(int N, int target);
 
 /* Measurement: run n >= 1 steps outside any graph with HIP events around
  * each kernel of the step (on the context's stream) and return the average

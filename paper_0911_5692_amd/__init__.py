@@ -12,12 +12,13 @@ from __future__ import annotations
 
 import importlib
 
-__all__ = ["Lattice", "Ensemble", "LeapfrogLoss", "autotune", "vacuum_fields", "stream_copy", "LfError", "inputs",
-           "workloads", "build"]
+__all__ = ["Lattice", "Ensemble", "LeapfrogLoss", "autotune", "ens_autotune", "vacuum_fields", "stream_copy",
+           "LfError", "inputs", "workloads", "build"]
 
 
 def __getattr__(name):
-    if name in ("Lattice", "Ensemble", "LeapfrogLoss", "autotune", "vacuum_fields", "stream_copy"):
+    if name in ("Lattice", "Ensemble", "LeapfrogLoss", "autotune", "ens_autotune", "vacuum_fields",
+                "stream_copy"):
         return getattr(importlib.import_module(".lattice", __name__), name)
     if name == "LfError":
         return importlib.import_module("._lib", __name__).LfError

@@ -81,6 +81,12 @@ SIGNATURES = {
                       ctypes.c_int),
     "lf_slab_sweep_sums": ([_vp, ctypes.c_int, ctypes.c_int] + [ctypes.POINTER(_vp)] * 4 + [_vp], ctypes.c_int),
     "lf_autotune_workspace_bytes": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "lf_ens_autotune_workspace_bytes": ([ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)],
+                                        ctypes.c_int),
+    "lf_ens_autotune": ([ctypes.c_int, ctypes.POINTER(Params), _vp, _vp, ctypes.c_size_t, ctypes.c_char_p,
+                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "lf_ens_zchunk": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "lf_autotune": ([ctypes.POINTER(Params), _vp, _vp, ctypes.c_size_t, ctypes.c_char_p, ctypes.POINTER(Params),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "lf_adj_workspace_bytes": ([ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int,

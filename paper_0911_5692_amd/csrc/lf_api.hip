@@ -11,6 +11,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 using namespace lf;
 
@@ -172,10 +173,12 @@ int validate(const lf_params *p)
     if (p->tile_y != 0 && p->tile_y != 1 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16)
         return fail(LF_EINVAL, "tile_y=%d: must be 0 (auto), 1 (plain), 4, 8 or 16", p->tile_y);
     if (p->zchunk < 0 || p->zchunk > 4096) return fail(LF_EINVAL, "zchunk=%d out of range", p->zchunk);
-    if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 128)
-        return fail(LF_EINVAL, "tile_x=%d: must be 0 (auto), 64 or 128", p->tile_x);
+    if (p->tile_x != 0 && p->tile_x != 32 && p->tile_x != 64 && p->tile_x != 128)
+        return fail(LF_EINVAL, "tile_x=%d: must be 0 (auto), 32, 64 or 128", p->tile_x);
     if (p->tile_x == 128 && p->tile_y != 4 && p->tile_y != 8)
         return fail(LF_EINVAL, "tile_x=128 needs tile_y 4 or 8");
+    if (p->tile_x == 32 && ((p->tile_y != 8 && p->tile_y != 16) || p->stencil == 27))
+        return fail(LF_EINVAL, "tile_x=32 needs tile_y 8 or 16 and the 7-point stencil");
     if (p->stencil != 0 && p->stencil != 7 && p->stencil != 27)
         return fail(LF_EINVAL, "stencil=%d: must be 0 or 7 (7-point) or 27 (27-point)", p->stencil);
     return LF_OK;
@@ -1202,8 +1205,9 @@ int candidates(const lf_params *p, lf_params *out, int cap)
     lf_params q = *p;
     q.tile_x = 0; q.tile_y = 1; q.zchunk = 0;
     out[n++] = q;
-    const int tiles[5][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}};
-    for (int t = 0; t < 5; ++t) {
+    const int tiles[7][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {128, 8}, {32, 8}, {32, 16}};
+    const int ntiles = stencil_of(p) == 27 ? 5 : 7;  // 32-wide tiles: 7-point sweep only
+    for (int t = 0; t < ntiles; ++t) {
         const int zs[9] = {0, 16, 32, 64, 128, p->N / 6, p->N / 4, p->N / 3, p->N / 2};
         int seen[9], ns = 0;
         for (int j = 0; j < 9; ++j) {
@@ -1308,6 +1312,7 @@ struct lf_ens {
     lf_ctx **sub;        // one context per realization, on slices of the workspace
     EnsEntry *tab;       // device table (workspace)
     int4 *items;         // device work list (workspace)
+    int *queue;          // device work counter of the persistent sweep (workspace)
     int nitems, grid;
     int cur;
     hipGraphExec_t g2, g1[2];
@@ -1322,6 +1327,10 @@ struct EnsLayout {
     size_t tab, items, total;
     int nitems;
 };
+
+// the sweep's work counters (8, 32 ints apart) and the 9 segment bounds
+constexpr int kXcdCount = 8;
+constexpr int kEnsQueueInts = kXcdCount * 32 + kXcdCount + 1;
 
 int ens_tile_y(const lf_params *p0) { return p0->tile_y ? p0->tile_y : 8; }
 int ens_tile_x(const lf_params *p0) { return p0->tile_x ? p0->tile_x : 64; }
@@ -1407,6 +1416,7 @@ int lf_ens_workspace_bytes(int R, const lf_params *per, size_t *out_bytes)
     delete[] so;
     off = align_up(off + (size_t)R * sizeof(EnsEntry));
     off = align_up(off + (size_t)nitems * sizeof(int4));
+    off = align_up(off + kEnsQueueInts * sizeof(int));
     *out_bytes = off;
     return LF_OK;
 }
@@ -1455,6 +1465,8 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     e->tab = (EnsEntry *)(ws + off);
     off = align_up(off + (size_t)R * sizeof(EnsEntry));
     e->items = (int4 *)(ws + off);
+    off = align_up(off + (size_t)nitems * sizeof(int4));
+    e->queue = (int *)(ws + off);
     e->nitems = nitems;
     EnsEntry *htab = new EnsEntry[R];
     int4 *hitems = new int4[nitems > 0 ? nitems : 1];
@@ -1484,13 +1496,61 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     }
     delete[] so;
     if (rc == LF_OK) {
-        // items with the most planes first: the persistent grid's last round
-        // is then made of the shortest items (each item keeps its partial row)
-        std::stable_sort(hitems, hitems + nitems,
-                         [&](const int4 &a, const int4 &b) { return htab[a.x].zchunk > htab[b.x].zchunk; });
+        // Split the items into one segment per XCD: whole z-chunks of a
+        // realization (all their tiles) go to one segment, assigned longest
+        // first to the segment with the least work so far; inside a segment
+        // the items with the most planes come first, a chunk's tiles in tile
+        // order (each item keeps its partial row, so no order changes a sum).
+        auto planes = [&](const int4 &it) {
+            const EnsEntry &t = htab[it.x];
+            const int z0 = it.y / (t.ntx * t.nty) * t.zchunk;
+            return t.N - z0 < t.zchunk ? t.N - z0 : t.zchunk;
+        };
+        auto chunk_of = [&](const int4 &it) { return it.y / (htab[it.x].ntx * htab[it.x].nty); };
+        struct Unit { int r, c, first, count, planes; };
+        std::vector<Unit> units;
+        for (int i = 0; i < nitems;) {
+            int j = i;
+            while (j < nitems && hitems[j].x == hitems[i].x && chunk_of(hitems[j]) == chunk_of(hitems[i])) ++j;
+            units.push_back(Unit{hitems[i].x, chunk_of(hitems[i]), i, j - i, planes(hitems[i])});
+            i = j;
+        }
+        std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) {
+            return (long long)a.count * a.planes > (long long)b.count * b.planes;
+        });
+        std::vector<int> bin(units.size());
+        long long load[kXcdCount] = {0};
+        for (size_t u = 0; u < units.size(); ++u) {
+            int best = 0;
+            for (int x = 1; x < kXcdCount; ++x)
+                if (load[x] < load[best]) best = x;
+            bin[u] = best;
+            load[best] += (long long)units[u].count * units[u].planes;
+        }
+        std::vector<int4> sorted;
+        sorted.reserve(nitems);
+        int seg[kXcdCount + 1];
+        for (int x = 0; x < kXcdCount; ++x) {
+            seg[x] = (int)sorted.size();
+            std::vector<size_t> mine;
+            for (size_t u = 0; u < units.size(); ++u)
+                if (bin[u] == x) mine.push_back(u);
+            std::stable_sort(mine.begin(), mine.end(), [&](size_t a, size_t b) {
+                if (units[a].planes != units[b].planes) return units[a].planes > units[b].planes;
+                return units[a].r != units[b].r ? units[a].r < units[b].r : units[a].c < units[b].c;
+            });
+            for (size_t u : mine)
+                for (int k = 0; k < units[u].count; ++k) sorted.push_back(hitems[units[u].first + k]);
+        }
+        seg[kXcdCount] = (int)sorted.size();
+        for (int i = 0; i < nitems; ++i) hitems[i] = sorted[i];
+        int hq[kEnsQueueInts] = {0};
+        for (int x = 0; x <= kXcdCount; ++x) hq[8 * 32 + x] = seg[x];
         hipError_t he = hipMemcpyAsync(e->tab, htab, (size_t)R * sizeof(EnsEntry), hipMemcpyHostToDevice, e->stream);
         if (he == hipSuccess)
             he = hipMemcpyAsync(e->items, hitems, (size_t)nitems * sizeof(int4), hipMemcpyHostToDevice, e->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(e->queue, hq, sizeof hq, hipMemcpyHostToDevice, e->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
         if (he != hipSuccess) rc = fail(LF_EHIP, "uploading the ensemble tables: %s", hipGetErrorString(he));
     }
@@ -1518,9 +1578,9 @@ namespace {
 
 void ens_enqueue_step(lf_ens *e, int parity, hipStream_t st)
 {
-    launch_aupdate_ens(e->tab, e->R, st);
-    launch_sweep_ens(e->stencil, e->dtype, e->tile_x, e->tile_y, e->beta, e->tab, e->items, e->nitems, e->grid,
-                     parity, st);
+    launch_aupdate_ens(e->tab, e->R, e->queue, st);
+    launch_sweep_ens(e->stencil, e->dtype, e->tile_x, e->tile_y, e->beta, e->tab, e->items, e->nitems, e->queue,
+                     e->grid, parity, st);
 }
 
 int ens_capture(lf_ens *e, int nsteps, int start, hipGraphExec_t *exec)
@@ -1650,6 +1710,211 @@ int lf_ens_get_fields(lf_ens *e, int r, void *f1, void *f2, void *v1, void *v2, 
     if (!e) return fail(LF_EINVAL, "ensemble is NULL");
     if (r < 0 || r >= e->R) return fail(LF_EINVAL, "realization %d out of range", r);
     return lf_get_fields(e->sub[r], f1, f2, v1, v2, out_dtype, synchronized);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- ensemble autotuner
+
+namespace {
+
+// z-chunk of an N-plane lattice for a target item length: the fewest equal
+// chunks of at most `target` planes (0 = the ensemble's default rule).
+int ens_zchunk_for(int N, int target)
+{
+    if (target <= 0 || target >= N) return target <= 0 ? 0 : N;
+    const int n = (N + target - 1) / target;
+    return (N + n - 1) / n;
+}
+
+// Cache key of an ensemble: the multiset of lattice sizes, "N:count,..." in
+// increasing N.  Returns 0 if it does not fit in `len` characters.
+int ens_key(int R, const lf_params *per, char *key, size_t len)
+{
+    int *ns = new int[R];
+    for (int r = 0; r < R; ++r) ns[r] = per[r].N;
+    std::sort(ns, ns + R);
+    size_t off = 0;
+    int ok = 1;
+    key[0] = 0;
+    for (int i = 0; i < R && ok;) {
+        int j = i;
+        while (j < R && ns[j] == ns[i]) ++j;
+        const int w = snprintf(key + off, len - off, "%s%d:%d", off ? "," : "", ns[i], j - i);
+        if (w < 0 || (size_t)w >= len - off) ok = 0;
+        else off += (size_t)w;
+        i = j;
+    }
+    delete[] ns;
+    return ok;
+}
+
+// Ensemble cache lines:
+// {"arch": "gfx950", "ensemble": "64:48,96:16,160:4", "dtype": 0, "beta": 4, "stencil": 7,
+//  "tile_x": 64, "tile_y": 8, "ztarget": 64, "ms": 0.25}
+int ens_cache_lookup(const char *path, const char *arch, const char *key, int dtype, int beta, int stencil,
+                     int *tx, int *ty, int *zt)
+{
+    if (!path) return 0;
+    FILE *f = fopen(path, "r");
+    if (!f) return 0;
+    char line[2048];
+    int found = 0;
+    while (fgets(line, sizeof line, f)) {
+        char a[64] = {0}, k[1200] = {0};
+        int dt, b, st, x, y, z;
+        double ms;
+        if (sscanf(line, " {\"arch\": \"%63[^\"]\", \"ensemble\": \"%1199[^\"]\", \"dtype\": %d, \"beta\": %d, "
+                         "\"stencil\": %d, \"tile_x\": %d, \"tile_y\": %d, \"ztarget\": %d, \"ms\": %lf",
+                   a, k, &dt, &b, &st, &x, &y, &z, &ms) == 9 &&
+            !strcmp(a, arch) && !strcmp(k, key) && dt == dtype && b == beta && st == stencil) {
+            *tx = x;
+            *ty = y;
+            *zt = z;
+            found = 1;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void ens_cache_append(const char *path, const char *arch, const char *key, int dtype, int beta, int stencil,
+                      int tx, int ty, int zt, double ms)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"arch\": \"%s\", \"ensemble\": \"%s\", \"dtype\": %d, \"beta\": %d, \"stencil\": %d, "
+               "\"tile_x\": %d, \"tile_y\": %d, \"ztarget\": %d, \"ms\": %.6f}\n",
+            arch, key, dtype, beta, stencil, tx, ty, zt, ms);
+    fclose(f);
+}
+
+struct EnsCand {
+    int tx, ty, zt;
+};
+
+// Candidates: every LDS tile (32-wide ones for the 7-point sweep only) with
+// target item lengths from 16 planes to whole lattices, plus the default
+// z-chunk rule; candidates giving the same chunks for every lattice as an
+// earlier one are dropped.
+int ens_candidates(int R, const lf_params *per, EnsCand *out, int cap)
+{
+    const int tiles[7][2] = {{64, 8}, {64, 4}, {64, 16}, {128, 4}, {128, 8}, {32, 8}, {32, 16}};
+    const int ntiles = stencil_of(&per[0]) == 27 ? 5 : 7;
+    const int targets[10] = {0, 16, 24, 32, 48, 64, 96, 128, 192, 1 << 20};
+    int n = 0;
+    for (int t = 0; t < ntiles; ++t)
+        for (int j = 0; j < 10 && n < cap; ++j) {
+            int dup = 0;
+            for (int i = 0; i < n && !dup; ++i) {
+                if (out[i].tx != tiles[t][0] || out[i].ty != tiles[t][1] || out[i].zt == 0 || targets[j] == 0)
+                    continue;
+                int same = 1;
+                for (int r = 0; r < R && same; ++r)
+                    same = ens_zchunk_for(per[r].N, out[i].zt) == ens_zchunk_for(per[r].N, targets[j]);
+                dup = same;
+            }
+            if (!dup) out[n++] = EnsCand{tiles[t][0], tiles[t][1], targets[j]};
+        }
+    return n;
+}
+
+// per with candidate c's tile and z-chunks (a realization's own zchunk wins)
+void ens_apply(int R, const lf_params *per, const EnsCand &c, lf_params *q)
+{
+    for (int r = 0; r < R; ++r) {
+        q[r] = per[r];
+        q[r].tile_x = c.tx;
+        q[r].tile_y = c.ty;
+        if (!per[r].zchunk) q[r].zchunk = ens_zchunk_for(per[r].N, c.zt);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lf_ens_zchunk(int N, int target) { return N >= 1 ? ens_zchunk_for(N, target) : 0; }
+
+int lf_ens_autotune_workspace_bytes(int R, const lf_params *per, size_t *out_bytes)
+{
+    int rc = ens_validate(R, per);
+    if (rc) return rc;
+    if (!out_bytes) return fail(LF_EINVAL, "out_bytes is NULL");
+    EnsCand cand[80];
+    const int n = ens_candidates(R, per, cand, 80);
+    lf_params *q = new lf_params[R];
+    size_t m = 0;
+    for (int i = 0; i < n && rc == LF_OK; ++i) {
+        ens_apply(R, per, cand[i], q);
+        size_t b = 0;
+        rc = lf_ens_workspace_bytes(R, q, &b);
+        m = b > m ? b : m;
+    }
+    delete[] q;
+    if (rc) return rc;
+    *out_bytes = m;
+    return LF_OK;
+}
+
+int lf_ens_autotune(int R, const lf_params *per, void *stream, void *workspace, size_t ws_bytes,
+                    const char *cache_path, int *tile_x, int *tile_y, int *ztarget, double *best_ms)
+{
+    int rc = ens_validate(R, per);
+    if (rc) return rc;
+    if (!tile_x || !tile_y || !ztarget) return fail(LF_EINVAL, "NULL output");
+    char arch[64], key[1200];
+    if ((rc = current_arch(arch, sizeof arch))) return rc;
+    const int have_key = ens_key(R, per, key, sizeof key);
+    const int dtype = per[0].dtype, beta = per[0].beta, stencil = stencil_of(&per[0]);
+    if (have_key && ens_cache_lookup(cache_path, arch, key, dtype, beta, stencil, tile_x, tile_y, ztarget)) {
+        if (best_ms) *best_ms = -1.0;
+        return LF_OK;
+    }
+    size_t need = 0;
+    if ((rc = lf_ens_autotune_workspace_bytes(R, per, &need))) return rc;
+    if ((rc = check_ptr(workspace, "workspace"))) return rc;
+    if (ws_bytes < need) return fail(LF_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    EnsCand cand[80];
+    const int n = ens_candidates(R, per, cand, 80);
+    lf_params *q = new lf_params[R];
+    double bms = 1e300;
+    int bi = -1;
+    for (int i = 0; i < n && rc == LF_OK; ++i) {
+        ens_apply(R, per, cand[i], q);
+        lf_ens *e = nullptr;
+        if ((rc = lf_ens_create(R, q, stream, workspace, ws_bytes, &e))) break;
+        for (int r = 0; r < R; ++r) {
+            lf_ctx *c = e->sub[r];
+            void *s4[4] = {c->buf[0][0], c->buf[0][1], c->buf[0][2], c->buf[0][3]};
+            launch_fill_synthetic(c->p.dtype, s4, c->p.N, c->S, c->stream);
+            launch_reduce(stencil_of(&c->p), c->p.dtype, s4[0], s4[1], c->p.N, c->S->bg_f, c->p.beta, c->part,
+                          c->sh.rows, c->stream);
+            c->inited = 1;
+            c->cur = 0;
+        }
+        double ms = 0.0;
+        const int steps = 40;
+        rc = lf_ens_step(e, 4);
+        if (!rc) rc = lf_ens_step(e, steps);
+        if (!rc) rc = lf_ens_last_step_ms(e, &ms);
+        lf_ens_destroy(e);
+        ms /= steps;
+        if (!rc && ms < bms) {
+            bms = ms;
+            bi = i;
+        }
+    }
+    delete[] q;
+    if (rc) return rc;
+    *tile_x = cand[bi].tx;
+    *tile_y = cand[bi].ty;
+    *ztarget = cand[bi].zt;
+    if (best_ms) *best_ms = bms;
+    if (have_key) ens_cache_append(cache_path, arch, key, dtype, beta, stencil, cand[bi].tx, cand[bi].ty,
+                                   cand[bi].zt, bms);
+    return LF_OK;
 }
 
 }  // extern "C"

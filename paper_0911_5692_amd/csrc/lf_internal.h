@@ -85,9 +85,11 @@ void launch_reduce(int stencil, int dtype, const void *d1, const void *d2, int N
 // tape (may be NULL): receives a copy of *S as it was before the update
 void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars *S,
                     CoefPair *C, hipStream_t st, DevScalars *tape = nullptr);
-void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st);
+// queue: the ensemble sweep's work counters (8, 32 ints apart), reset to 0
+// by this kernel, followed by the 9 segment bounds of the item list
+void launch_aupdate_ens(const EnsEntry *tab, int R, int *queue, hipStream_t st);
 void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
-                      const int4 *items, int nitems, int grid, int parity, hipStream_t st);
+                      const int4 *items, int nitems, int *queue, int grid, int parity, hipStream_t st);
 void launch_sweep_plain(int stencil, int dtype, int beta, const void *const in[4], void *const out[4], int N,
                         const CoefPair *C, hipStream_t st);
 // Arrays of one sweep over planes [0, nz) of an N x N x nz z-slab: the
@@ -118,7 +120,7 @@ void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void 
                         void *const out[4], int N, int zchunk, const CoefPair *C, double *part,
                         hipStream_t st);
 void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
-                        const int4 *items, int nitems, int grid, int parity, hipStream_t st);
+                        const int4 *items, int nitems, int *queue, int grid, int parity, hipStream_t st);
 int sweep_lds27_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta);
 // Resident blocks per CU of the LDS sweep instantiation (0 if unknown, e.g.
 // no device).

@@ -297,8 +297,12 @@ __global__ void __launch_bounds__(kStage2Threads) k_aupdate(const double *part, 
 }
 
 // Ensemble: block r updates realization r.
-__global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *tab)
+__global__ void __launch_bounds__(kStage2Threads) k_aupdate_ens(const EnsEntry *tab, int *queue)
 {
+    // the sweep that follows takes its work items from these counters (one
+    // per XCD, 32 ints apart)
+    if (blockIdx.x == 0 && threadIdx.x < 8)
+        __hip_atomic_store(queue + 32 * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const EnsEntry &e = tab[blockIdx.x];
     aupdate_block(e.part, e.rows, e.P, e.S, e.Cw, nullptr);
 }
@@ -660,9 +664,9 @@ void launch_aupdate(const double *part, int nblk, const DevParams *P, DevScalars
     hipLaunchKernelGGL(k_aupdate, dim3(1), dim3(kStage2Threads), 0, st, part, nblk, P, S, C, tape);
 }
 
-void launch_aupdate_ens(const EnsEntry *tab, int R, hipStream_t st)
+void launch_aupdate_ens(const EnsEntry *tab, int R, int *queue, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_aupdate_ens, dim3(R), dim3(kStage2Threads), 0, st, tab);
+    hipLaunchKernelGGL(k_aupdate_ens, dim3(R), dim3(kStage2Threads), 0, st, tab, queue);
 }
 
 // Launch shape of k_diag_march for an N^3 lattice: tiles of 64 x 4, z-chunks

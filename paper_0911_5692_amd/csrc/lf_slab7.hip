@@ -51,7 +51,7 @@ void slab_b(int beta, const SweepIO &io, int N, int zchunk, const CoefPair *C, d
     }
 }
 
-// Supported tiles (x by y): 64x4, 64x8, 64x16, 128x4, 128x8.
+// Supported tiles (x by y): 32x8, 32x16, 64x4, 64x8, 64x16, 128x4, 128x8.
 template <typename T>
 void slab_y(int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchunk, const CoefPair *C,
             double *part, hipStream_t st)
@@ -59,6 +59,11 @@ void slab_y(int tile_x, int tile_y, int beta, const SweepIO &io, int N, int zchu
     if (tile_x == 128) {
         if (tile_y == 4) slab_b<T, 128, 4>(beta, io, N, zchunk, C, part, st);
         else slab_b<T, 128, 8>(beta, io, N, zchunk, C, part, st);
+        return;
+    }
+    if (tile_x == 32) {
+        if (tile_y == 8) slab_b<T, 32, 8>(beta, io, N, zchunk, C, part, st);
+        else slab_b<T, 32, 16>(beta, io, N, zchunk, C, part, st);
         return;
     }
     switch (tile_y) {

@@ -108,14 +108,16 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_lds(
                                                         part + (size_t)tile * kNPart);
 }
 
-// Ensemble: a persistent grid walks a static list of work items
-// (realization, tile, z-chunk); item i writes partial row i of its
-// realization's row range.  All realizations advance one step per launch.
+// Ensemble: a persistent grid takes the work items (realization, tile,
+// z-chunk) of a static list from per-XCD segments (for_each_item); each item
+// writes its own partial row of its realization.  All realizations advance
+// one step per launch.
 template <typename T, int NH, int TX, int TY>
 __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_ens(
-    const EnsEntry *__restrict__ tab, const int4 *__restrict__ items, const int nitems, const int parity)
+    const EnsEntry *__restrict__ tab, const int4 *__restrict__ items, const int nitems, int *queue,
+    const int parity)
 {
-    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    for_each_item(queue, nitems, [&](int i) {
         const int4 it = items[i];  // x: realization, y: tile index within it, z: partial row
         const EnsEntry &e = tab[it.x];
         const int tx = it.y % e.ntx, r2 = it.y / e.ntx, ty = r2 % e.nty, tz = r2 / e.nty;
@@ -126,8 +128,7 @@ __global__ void __launch_bounds__(256, LF_SWEEP_MIN_WAVES) k_sweep_ens(
                                                             out[3], e.N, ZPlanes<T>{}, tx * TX, ty * TY, z0,
                                                             min(z0 + e.zchunk, e.N), e.C,
                                                             e.part + (size_t)it.z * kNPart);
-        __syncthreads();  // LDS is reused by the next item
-    }
+    });
 }
 
 // ------------------------------------------------------------ launchers
@@ -200,7 +201,7 @@ static void sweep_lds_b(int beta, const void *const in[4], void *const out[4], i
     }
 }
 
-// Supported tiles (x by y): 64x4, 64x8, 64x16, 128x4, 128x8.
+// Supported tiles (x by y): 32x8, 32x16, 64x4, 64x8, 64x16, 128x4, 128x8.
 template <typename T>
 static void sweep_lds_y(int tile_x, int tile_y, int beta, const void *const in[4], void *const out[4],
                         int N, int zchunk, const CoefPair *C, double *part, hipStream_t st)
@@ -208,6 +209,11 @@ static void sweep_lds_y(int tile_x, int tile_y, int beta, const void *const in[4
     if (tile_x == 128) {
         if (tile_y == 4) sweep_lds_b<T, 128, 4>(beta, in, out, N, zchunk, C, part, st);
         else sweep_lds_b<T, 128, 8>(beta, in, out, N, zchunk, C, part, st);
+        return;
+    }
+    if (tile_x == 32) {
+        if (tile_y == 8) sweep_lds_b<T, 32, 8>(beta, in, out, N, zchunk, C, part, st);
+        else sweep_lds_b<T, 32, 16>(beta, in, out, N, zchunk, C, part, st);
         return;
     }
     switch (tile_y) {
@@ -236,6 +242,7 @@ template <typename T>
 static int occ_y(int tile_x, int tile_y, int beta)
 {
     if (tile_x == 128) return tile_y == 4 ? occ_b<T, 128, 4>(beta) : occ_b<T, 128, 8>(beta);
+    if (tile_x == 32) return tile_y == 8 ? occ_b<T, 32, 8>(beta) : occ_b<T, 32, 16>(beta);
     switch (tile_y) {
     case 4: return occ_b<T, 64, 4>(beta);
     case 8: return occ_b<T, 64, 8>(beta);
@@ -250,47 +257,54 @@ int sweep_lds_blocks_per_cu(int stencil, int dtype, int tile_x, int tile_y, int 
 }
 
 template <typename T, int NH, int TX, int TY>
-static void sweep_ens_t(const EnsEntry *tab, const int4 *items, int nitems, int grid, int parity,
+static void sweep_ens_t(const EnsEntry *tab, const int4 *items, int nitems, int *queue, int grid, int parity,
                         hipStream_t st)
 {
-    hipLaunchKernelGGL((k_sweep_ens<T, NH, TX, TY>), dim3(grid), dim3(256), 0, st, tab, items, nitems, parity);
+    hipLaunchKernelGGL((k_sweep_ens<T, NH, TX, TY>), dim3(grid), dim3(256), 0, st, tab, items, nitems, queue,
+                       parity);
 }
 
 template <typename T, int TX, int TY>
-static void sweep_ens_b(int beta, const EnsEntry *tab, const int4 *items, int nitems, int grid,
+static void sweep_ens_b(int beta, const EnsEntry *tab, const int4 *items, int nitems, int *queue, int grid,
                         int parity, hipStream_t st)
 {
     switch (beta) {
-    case 2: sweep_ens_t<T, 1, TX, TY>(tab, items, nitems, grid, parity, st); break;
-    case 3: sweep_ens_t<T, 2, TX, TY>(tab, items, nitems, grid, parity, st); break;
-    case 4: sweep_ens_t<T, 3, TX, TY>(tab, items, nitems, grid, parity, st); break;
-    case 5: sweep_ens_t<T, 4, TX, TY>(tab, items, nitems, grid, parity, st); break;
-    default: sweep_ens_t<T, 5, TX, TY>(tab, items, nitems, grid, parity, st); break;
+    case 2: sweep_ens_t<T, 1, TX, TY>(tab, items, nitems, queue, grid, parity, st); break;
+    case 3: sweep_ens_t<T, 2, TX, TY>(tab, items, nitems, queue, grid, parity, st); break;
+    case 4: sweep_ens_t<T, 3, TX, TY>(tab, items, nitems, queue, grid, parity, st); break;
+    case 5: sweep_ens_t<T, 4, TX, TY>(tab, items, nitems, queue, grid, parity, st); break;
+    default: sweep_ens_t<T, 5, TX, TY>(tab, items, nitems, queue, grid, parity, st); break;
     }
 }
 
+// Supported tiles (x by y): 32x8, 32x16, 64x4, 64x8, 64x16, 128x4, 128x8.
 template <typename T>
 static void sweep_ens_y(int tile_x, int tile_y, int beta, const EnsEntry *tab, const int4 *items,
-                        int nitems, int grid, int parity, hipStream_t st)
+                        int nitems, int *queue, int grid, int parity, hipStream_t st)
 {
     if (tile_x == 128) {
-        if (tile_y == 4) sweep_ens_b<T, 128, 4>(beta, tab, items, nitems, grid, parity, st);
-        else sweep_ens_b<T, 128, 8>(beta, tab, items, nitems, grid, parity, st);
+        if (tile_y == 4) sweep_ens_b<T, 128, 4>(beta, tab, items, nitems, queue, grid, parity, st);
+        else sweep_ens_b<T, 128, 8>(beta, tab, items, nitems, queue, grid, parity, st);
+        return;
+    }
+    if (tile_x == 32) {
+        if (tile_y == 8) sweep_ens_b<T, 32, 8>(beta, tab, items, nitems, queue, grid, parity, st);
+        else sweep_ens_b<T, 32, 16>(beta, tab, items, nitems, queue, grid, parity, st);
         return;
     }
     switch (tile_y) {
-    case 4: sweep_ens_b<T, 64, 4>(beta, tab, items, nitems, grid, parity, st); break;
-    case 8: sweep_ens_b<T, 64, 8>(beta, tab, items, nitems, grid, parity, st); break;
-    default: sweep_ens_b<T, 64, 16>(beta, tab, items, nitems, grid, parity, st); break;
+    case 4: sweep_ens_b<T, 64, 4>(beta, tab, items, nitems, queue, grid, parity, st); break;
+    case 8: sweep_ens_b<T, 64, 8>(beta, tab, items, nitems, queue, grid, parity, st); break;
+    default: sweep_ens_b<T, 64, 16>(beta, tab, items, nitems, queue, grid, parity, st); break;
     }
 }
 
 void launch_sweep_ens(int stencil, int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
-                      const int4 *items, int nitems, int grid, int parity, hipStream_t st)
+                      const int4 *items, int nitems, int *queue, int grid, int parity, hipStream_t st)
 {
-    if (stencil == 27) launch_sweep_ens27(dtype, tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
-    else if (dtype == 0) sweep_ens_y<float>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
-    else sweep_ens_y<double>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+    if (stencil == 27) launch_sweep_ens27(dtype, tile_x, tile_y, beta, tab, items, nitems, queue, grid, parity, st);
+    else if (dtype == 0) sweep_ens_y<float>(tile_x, tile_y, beta, tab, items, nitems, queue, grid, parity, st);
+    else sweep_ens_y<double>(tile_x, tile_y, beta, tab, items, nitems, queue, grid, parity, st);
 }
 
 void launch_sweep_lds(int stencil, int dtype, int tile_x, int tile_y, int beta, const void *const in[4],

@@ -64,9 +64,10 @@ __global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_lds27(
 
 template <typename T, int NH, int TX, int TY>
 __global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_ens27(
-    const EnsEntry *__restrict__ tab, const int4 *__restrict__ items, const int nitems, const int parity)
+    const EnsEntry *__restrict__ tab, const int4 *__restrict__ items, const int nitems, int *queue,
+    const int parity)
 {
-    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    for_each_item(queue, nitems, [&](int i) {
         const int4 it = items[i];  // x: realization, y: tile index within it, z: partial row
         const EnsEntry &e = tab[it.x];
         const int tx = it.y % e.ntx, r2 = it.y / e.ntx, ty = r2 % e.nty, tz = r2 / e.nty;
@@ -75,9 +76,8 @@ __global__ void __launch_bounds__(256, LF_SWEEP27_WAVES(T)) k_sweep_ens27(
         T *const *out = (T *const *)e.buf[parity ^ 1];
         sweep_tile27<T, NH, TX, TY, false>(in[0], in[1], in[2], in[3], out[0], out[1], out[2], out[3], e.N,
                                            ZPlanes<T>{}, tx * TX, ty * TY, z0, min(z0 + e.zchunk, e.N), e.C,
-                                    e.part + (size_t)it.z * kNPart);
-        __syncthreads();  // LDS is reused by the next item
-    }
+                                           e.part + (size_t)it.z * kNPart);
+    });
 }
 
 // ------------------------------------------------------------ launchers
@@ -102,15 +102,15 @@ void lds27_t(int tile_x, int tile_y, int beta, const void *const in[4], void *co
 }
 
 template <typename T>
-void ens27_t(int tile_x, int tile_y, int beta, const EnsEntry *tab, const int4 *items, int nitems, int grid,
-             int parity, hipStream_t st)
+void ens27_t(int tile_x, int tile_y, int beta, const EnsEntry *tab, const int4 *items, int nitems, int *queue,
+             int grid, int parity, hipStream_t st)
 {
     with_tile(tile_x, tile_y, [&](auto tx, auto ty) {
         constexpr int TX = decltype(tx)::value, TY = decltype(ty)::value;
         with_nh(beta, [&](auto nh) {
             constexpr int NH = decltype(nh)::value;
             hipLaunchKernelGGL((k_sweep_ens27<T, NH, TX, TY>), dim3(grid), dim3(256), 0, st, tab, items, nitems,
-                               parity);
+                               queue, parity);
         });
     });
 }
@@ -141,10 +141,10 @@ void launch_sweep_lds27(int dtype, int tile_x, int tile_y, int beta, const void 
 }
 
 void launch_sweep_ens27(int dtype, int tile_x, int tile_y, int beta, const EnsEntry *tab,
-                        const int4 *items, int nitems, int grid, int parity, hipStream_t st)
+                        const int4 *items, int nitems, int *queue, int grid, int parity, hipStream_t st)
 {
-    if (dtype == 0) ens27_t<float>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
-    else ens27_t<double>(tile_x, tile_y, beta, tab, items, nitems, grid, parity, st);
+    if (dtype == 0) ens27_t<float>(tile_x, tile_y, beta, tab, items, nitems, queue, grid, parity, st);
+    else ens27_t<double>(tile_x, tile_y, beta, tab, items, nitems, queue, grid, parity, st);
 }
 
 int sweep_lds27_blocks_per_cu(int dtype, int tile_x, int tile_y, int beta)

@@ -103,6 +103,47 @@ inline ZPlanes<T> planes_of(const SweepIO &io)
     return zp;
 }
 
+// Work item loop of the persistent ensemble sweeps.  The items are split
+// into one segment per XCD (items seg[x] .. seg[x+1] - 1), each holding whole z-chunks
+// of some realizations, longest first; a block takes the next item of its own
+// XCD's segment (hardware places block b on XCD b mod 8) from that segment's
+// counter, so the tiles of one chunk run together on one L2 and find their
+// neighbours' halo rows there.  When its segment is used up it takes items of
+// the other segments in turn.  queue holds the counters (queue[32 x], 128
+// bytes apart), reset to 0 by the batched scale-factor kernel that runs
+// before every sweep, followed by seg[0..8].  Every thread of the block sees the same index; fn(i) runs for
+// each item.
+constexpr int kEnsXcd = 8, kEnsQueueStride = 32;
+
+template <typename F>
+__device__ inline void for_each_item(int *queue, int nitems, F &&fn)
+{
+    const int *seg = queue + kEnsXcd * kEnsQueueStride;  // segment bounds follow the counters
+    __shared__ int s_item;
+    const int home = blockIdx.x % kEnsXcd;
+    int k = 0;  // thread 0: segments used up so far, own segment first
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int item = -1;
+            while (k < kEnsXcd) {
+                const int x = (home + k) % kEnsXcd;
+                const int j = seg[x] + atomicAdd(queue + x * kEnsQueueStride, 1);
+                if (j < seg[x + 1] && j < nitems) {
+                    item = j;
+                    break;
+                }
+                ++k;
+            }
+            s_item = item;
+        }
+        __syncthreads();
+        const int i = s_item;
+        if (i < 0) break;
+        fn(i);
+        __syncthreads();  // LDS (and s_item) are reused by the next item
+    }
+}
+
 // Hardware places block b on XCD (b mod 8).  Give each XCD a contiguous range
 // of logical tiles, so that tiles sharing halo rows run on the same L2.
 __device__ inline int xcd_remap(int b, int nb)

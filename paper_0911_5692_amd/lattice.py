@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import shutil
 
 import torch
 
@@ -29,6 +30,16 @@ def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, shape) -> ctypes.c_void_p:
 
 DEFAULT_TUNE_CACHE = os.environ.get(
     "LF_AUTOTUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.jsonl"))
+# Choices the autotuners made on an MI355X (gfx950) for the benchmark's
+# workloads; a new default cache starts as a copy of them.
+SEED_TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_seed_gfx950.jsonl")
+
+
+def _cache(path: str | None) -> str | None:
+    """The cache file to use: the default one is created from the seed."""
+    if path and path == DEFAULT_TUNE_CACHE and not os.path.exists(path) and os.path.exists(SEED_TUNE_CACHE):
+        shutil.copyfile(SEED_TUNE_CACHE, path)
+    return path
 
 
 def autotune(N: int, L: float, dt: float, beta: int, c1: float, G: float, r: float, s: float,
@@ -45,6 +56,7 @@ def autotune(N: int, L: float, dt: float, beta: int, c1: float, G: float, r: flo
     ws = torch.empty(size.value, dtype=torch.uint8, device=device)
     stream = torch.cuda.current_stream(torch.device(device))
     best, ms = Params(), ctypes.c_double()
+    cache_path = _cache(cache_path)
     check(lib().lf_autotune(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(ws.data_ptr()),
                             size.value, cache_path.encode() if cache_path else None, ctypes.byref(best),
                             ctypes.byref(ms)))
@@ -405,24 +417,60 @@ def _report_dict(rep: Report) -> dict:
                 G1=rep.Gr[0], G2=rep.Gr[1], P=rep.P, rho=rep.rho, R=rep.R, status=rep.status)
 
 
+def _ens_params(members, dtype, tile_x=0, tile_y=0, zchunks=None):
+    arr = (Params * len(members))()
+    for i, m in enumerate(members):
+        zc = int(zchunks[i]) if zchunks is not None else 0
+        arr[i] = Params(int(m["N"]), _DT[dtype], float(m["L"]), float(m["dt"]), int(m["beta"]), 0,
+                        float(m["c1"]), float(m["G"]), float(m["r"]), float(m["s"]),
+                        float(m["kappa2"]), int(tile_y), zc, int(tile_x), int(m.get("stencil", 7)))
+    return arr
+
+
+def ens_autotune(members, dtype: torch.dtype = torch.float32, device="cuda",
+                 cache_path: str | None = DEFAULT_TUNE_CACHE) -> dict:
+    """Fastest ensemble launch shape for these realizations on the current
+    device (liblf's lf_ens_autotune; cached per architecture and multiset of
+    lattice sizes).  Returns dict(tile_x, tile_y, ztarget, zchunks, ms), with
+    zchunks the per-realization z-chunks of the target (ms = -1 on a cache
+    hit)."""
+    arr = _ens_params(members, dtype)
+    R = len(members)
+    size = ctypes.c_size_t()
+    check(lib().lf_ens_autotune_workspace_bytes(R, arr, ctypes.byref(size)))
+    ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    tx, ty, zt, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    cache_path = _cache(cache_path)
+    check(lib().lf_ens_autotune(R, arr, ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(ws.data_ptr()),
+                                size.value, cache_path.encode() if cache_path else None, ctypes.byref(tx),
+                                ctypes.byref(ty), ctypes.byref(zt), ctypes.byref(ms)))
+    del ws
+    zchunks = [lib().lf_ens_zchunk(int(m["N"]), zt.value) for m in members]
+    return dict(tile_x=tx.value, tile_y=ty.value, ztarget=zt.value, zchunks=zchunks, ms=ms.value)
+
+
 class Ensemble:
     """R independent lattices stepped together by liblf's batched kernels.
 
     members: list of dicts with the Lattice keyword arguments N, L, dt, beta,
     c1, G, r, s, kappa2 and optionally stencil (dtype, beta and stencil
-    common to all)."""
+    common to all).  tuned: take the tile and z-chunks from the ensemble
+    autotuner (its cache, or a tuning run on a miss; a string is the cache
+    path) unless a tile or z-chunks are given."""
 
     def __init__(self, members, dtype: torch.dtype = torch.float32, device="cuda", tile_x: int = 0,
-                 tile_y: int = 0, zchunks=None, stream: torch.cuda.Stream | None = None):
+                 tile_y: int = 0, zchunks=None, stream: torch.cuda.Stream | None = None,
+                 tuned: bool | str = False):
         self.R = len(members)
         self.dtype = dtype
         self.device = torch.device(device)
-        arr = (Params * self.R)()
-        for i, m in enumerate(members):
-            zc = int(zchunks[i]) if zchunks is not None else 0
-            arr[i] = Params(int(m["N"]), _DT[dtype], float(m["L"]), float(m["dt"]), int(m["beta"]), 0,
-                            float(m["c1"]), float(m["G"]), float(m["r"]), float(m["s"]),
-                            float(m["kappa2"]), int(tile_y), zc, int(tile_x), int(m.get("stencil", 7)))
+        self.tuning = None
+        if tuned and not (tile_x or tile_y or zchunks is not None):
+            self.tuning = ens_autotune(members, dtype, device,
+                                       cache_path=tuned if isinstance(tuned, str) else DEFAULT_TUNE_CACHE)
+            tile_x, tile_y, zchunks = self.tuning["tile_x"], self.tuning["tile_y"], self.tuning["zchunks"]
+        arr = _ens_params(members, dtype, tile_x, tile_y, zchunks)
         self.params = arr
         self.Ns = [int(m["N"]) for m in members]
         size = ctypes.c_size_t()

@@ -2,9 +2,11 @@
 
 Two steps, each its own process:
 
-  run        a plain device copy of known size (the counter calibration),
-             then a few leapfrog steps of a workload at its benchmark launch
-             shape; meant to run under
+  run        a plain device copy of known size (the counter calibration) and
+             a read-only sum over the same bytes (its cross-check), then a
+             few leapfrog steps of a workload at its benchmark launch shape
+             (or of the 68-lattice ensemble at its autotuned shape); meant to
+             run under
                rocprofv3 --pmc FETCH_SIZE ...   and again with   --pmc WRITE_SIZE
   summarize  reads the two counter CSVs (and optionally a --kernel-trace
              --stats CSV), scales each counter by what it reads for the copy,
@@ -48,21 +50,54 @@ def sweep_source_hash(stencil: int = 7) -> str:
     return h.hexdigest()[:16]
 
 
+ENSEMBLE = "ensemble"  # the 68-lattice workload of uneven sizes (48 x 64^3 + 16 x 96^3 + 4 x 160^3)
+
+
+def _calibration_kernels() -> None:
+    """A device copy of COPY_MIB MiB (reads and writes that much) and a
+    read-only sum over the same bytes (reads them once, writes 4 bytes)."""
+    import torch
+
+    n = COPY_MIB * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s = a.sum()
+    torch.cuda.synchronize()
+    del a, b, s
+
+
+def run_ensemble(steps: int) -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_0911_5692_amd import Ensemble
+    from paper_0911_5692_amd import workloads as W
+
+    _calibration_kernels()
+    members = W.ensemble_members()
+    ens = Ensemble([m.model() for m in members], dtype=torch.float32, tuned=True)
+    for r, m in enumerate(members):
+        ic = W.make_inputs(m, realization=r)
+        ens.init_physical(r, *(torch.from_numpy(ic[k]).to("cuda") for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+    ens.step(steps)
+    torch.cuda.synchronize()
+    print(f"profile run done: ensemble {steps} steps, shape {ens.tuning}", flush=True)
+
+
 def run(workload: str, steps: int) -> None:
     import torch
 
+    if workload == ENSEMBLE:
+        run_ensemble(steps)
+        return
     sys.path.insert(0, ROOT)
     from paper_0911_5692_amd import Lattice
     from paper_0911_5692_amd import workloads as W
 
     w = W.WORKLOADS[workload]
     shape = W.BENCH_SHAPES.get(w.name, {})
-    n = COPY_MIB * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)  # the calibration copy: reads and writes COPY_MIB MiB
-    torch.cuda.synchronize()
-    del a, b
+    _calibration_kernels()
     N = w.N
     g = torch.Generator(device="cuda")
     g.manual_seed(0)
@@ -102,24 +137,34 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
     sys.path.insert(0, ROOT)
     from paper_0911_5692_amd import workloads as W
 
-    w = W.WORKLOADS[workload]
-    esize = 4 if w.dtype == "f32" else 8
-    alg = 8 * esize * w.sites
+    if workload == ENSEMBLE:
+        sites = sum(m.sites for m in W.ensemble_members())
+        alg, stencil, shape = 32 * sites, 7, "autotuned (profile run log)"
+        is_sweep = lambda k: "k_sweep_ens" in k
+    else:
+        w = W.WORKLOADS[workload]
+        esize = 4 if w.dtype == "f32" else 8
+        alg, stencil, shape = 8 * esize * w.sites, w.stencil, W.BENCH_SHAPES.get(w.name, {})
+        is_sweep = lambda k: "k_sweep" in k
     copy_bytes = COPY_MIB * (1 << 20)
     is_copy = lambda k: "copy" in k.lower() and "lf::" not in k
-    is_sweep = lambda k: "k_sweep" in k
+    is_sum = lambda k: "reduce_kernel" in k
     fpath, wpath = _find(fetch_dir, "counter_collection.csv"), _find(write_dir, "counter_collection.csv")
     f_copy = _counter(fpath, "FETCH_SIZE", is_copy)
     w_copy = _counter(wpath, "WRITE_SIZE", is_copy)
+    f_sum = _counter(fpath, "FETCH_SIZE", is_sum)
     f_sweep = _counter(fpath, "FETCH_SIZE", is_sweep)
     w_sweep = _counter(wpath, "WRITE_SIZE", is_sweep)
-    # the calibration copy is the largest copy dispatch
+    # the calibration copy is the largest copy dispatch, the read-only sum the
+    # largest reduction
     fc, wc = max(f_copy) * 1024.0, max(w_copy) * 1024.0
     kf, kw = copy_bytes / fc, copy_bytes / wc
+    kf_sum = copy_bytes / (max(f_sum) * 1024.0) if f_sum else None
     fetch = sum(f_sweep) / len(f_sweep) * 1024.0 * kf
     write = sum(w_sweep) / len(w_sweep) * 1024.0 * kw
-    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(w.stencil),
-               launch_shape=W.BENCH_SHAPES.get(w.name, {}), algorithmic_bytes_per_launch=alg,
+    res = dict(workload=workload, sweep_source_hash=sweep_source_hash(stencil),
+               launch_shape=shape, algorithmic_bytes_per_launch=alg,
+               fetch_calibration_read_only=kf_sum,
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_calibration=kf, write_calibration=kw,
                fetch_over_algorithmic_reads=fetch / (alg / 2), write_over_algorithmic_writes=write / (alg / 2),
@@ -148,7 +193,11 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
             fh.write(f"    {c}\n")
         fh.write(f"\nCalibration: a device copy of {COPY_MIB} MiB reads FETCH_SIZE = {fc / 1024:.1f} KiB "
                  f"and WRITE_SIZE = {wc / 1024:.1f} KiB, so the counters are scaled by "
-                 f"{kf:.4f} (fetch) and {kw:.4f} (write).\n\n")
+                 f"{kf:.4f} (fetch) and {kw:.4f} (write).")
+        if kf_sum:
+            fh.write(f"  Cross-check: a read-only sum over the same {COPY_MIB} MiB reads FETCH_SIZE = "
+                     f"{max(f_sum):.1f} KiB, a fetch factor of {kf_sum:.4f}.")
+        fh.write("\n\n")
         fh.write("| quantity | per sweep launch |\n|---|---|\n")
         fh.write(f"| algorithmic bytes (32 B/site FP32) | {alg / 1e9:.4f} GB |\n")
         fh.write(f"| HBM fetch (scaled) | {fetch / 1e9:.4f} GB = {res['fetch_over_algorithmic_reads']:.3f} x algorithmic reads |\n")
@@ -187,7 +236,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
-    r.add_argument("--workload", default="m2phi2_512c_f32")
+    r.add_argument("--workload", default="m2phi2_512c_f32", help="a workload name, or 'ensemble'")
     r.add_argument("--steps", type=int, default=4)
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="m2phi2_512c_f32")

@@ -140,6 +140,9 @@ def test_vacuum_spec_rejected_before_any_device_call(LB, kw, frag):
 def test_spectrum_arguments_checked_before_any_device_call(LB):
     lib = LB.lib()
     assert lib.lf_spectrum_bins(0) == 0 and lib.lf_spectrum_bins(512) == 444
+    # ensemble z-chunk of a target item length: fewest equal chunks of at most target planes
+    assert [lib.lf_ens_zchunk(n, t) for n, t in ((160, 64), (96, 48), (64, 0), (64, 1 << 20), (160, 80), (7, 3))] \
+        == [54, 48, 0, 64, 80, 3]
     buf = (ctypes.c_double * 8)()
     assert lib.lf_spectrum(None, 0, 4, buf, buf, ctypes.c_void_p(0x100000), 1 << 20) == LB.LF_EINVAL
     assert "ctx" in lib.lf_last_error().decode()

@@ -172,10 +172,12 @@ def test_step_before_init_is_a_state_error():
     assert ei.value.code == 1
 
 
-SHAPES7 = [dict(tile_y=1), dict(tile_x=64, tile_y=4, zchunk=8), dict(tile_x=64, tile_y=8, zchunk=13),
-           dict(tile_x=64, tile_y=16, zchunk=48), dict(tile_x=128, tile_y=4, zchunk=7),
-           dict(tile_x=128, tile_y=8, zchunk=0)]
-SHAPES27 = SHAPES7[1:]  # the plain 27-point variant sums its stencil in another order
+SHAPES27 = [dict(tile_x=64, tile_y=4, zchunk=8), dict(tile_x=64, tile_y=8, zchunk=13),
+            dict(tile_x=64, tile_y=16, zchunk=48), dict(tile_x=128, tile_y=4, zchunk=7),
+            dict(tile_x=128, tile_y=8, zchunk=0)]
+# the 7-point sweep also has 32-wide tiles; the plain 27-point variant sums
+# its stencil in another order, so only the 7-point list holds the plain sweep
+SHAPES7 = [dict(tile_y=1)] + SHAPES27 + [dict(tile_x=32, tile_y=8, zchunk=11), dict(tile_x=32, tile_y=16, zchunk=0)]
 
 
 @pytest.mark.parametrize("stencil", [7, 27])
