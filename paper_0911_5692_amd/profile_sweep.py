@@ -5,8 +5,8 @@ Two steps, each its own process:
   run        a plain device copy of known size (the counter calibration) and
              a read-only sum over the same bytes (its cross-check), then a
              few leapfrog steps of a workload at its benchmark launch shape
-             (or of the 68-lattice ensemble at its autotuned shape); meant to
-             run under
+             (or of the 68-lattice ensemble at its autotuned shape, or the
+             adjoint of the 128^3 workload); meant to run under
                rocprofv3 --pmc FETCH_SIZE ...   and again with   --pmc WRITE_SIZE
   summarize  reads the two counter CSVs (and optionally a --kernel-trace
              --stats CSV), scales each counter by what it reads for the copy,
@@ -51,6 +51,7 @@ def sweep_source_hash(stencil: int = 7) -> str:
 
 
 ENSEMBLE = "ensemble"  # the 68-lattice workload of uneven sizes (48 x 64^3 + 16 x 96^3 + 4 x 160^3)
+ADJOINT = "adjoint"    # the 128^3 adjoint workload: 500 steps, checkpoints every 50, forward + backward
 
 
 def _calibration_kernels() -> None:
@@ -85,11 +86,32 @@ def run_ensemble(steps: int) -> None:
     print(f"profile run done: ensemble {steps} steps, shape {ens.tuning}", flush=True)
 
 
+def run_adjoint() -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_0911_5692_amd import Lattice
+    from paper_0911_5692_amd import workloads as W
+
+    _calibration_kernels()
+    w = W.CFG5
+    ic = W.make_inputs(w)
+    lat = Lattice(**w.model(), dtype=torch.float32)
+    lat.init_physical(*(torch.from_numpy(ic[k]).to("cuda") for k in ("f1", "f2", "u1", "u2")), ic["a0"])
+    lat.adjoint_forward(w.steps, 50)
+    lat.adjoint_backward(1.0)
+    torch.cuda.synchronize()
+    print(f"profile run done: adjoint of {w.name}, {w.steps} steps, K = 50", flush=True)
+
+
 def run(workload: str, steps: int) -> None:
     import torch
 
     if workload == ENSEMBLE:
         run_ensemble(steps)
+        return
+    if workload == ADJOINT:
+        run_adjoint()
         return
     sys.path.insert(0, ROOT)
     from paper_0911_5692_amd import Lattice
@@ -140,11 +162,22 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
     if workload == ENSEMBLE:
         sites = sum(m.sites for m in W.ensemble_members())
         alg, stencil, shape = 32 * sites, 7, "autotuned (profile run log)"
+        alg_read = alg / 2
         is_sweep = lambda k: "k_sweep_ens" in k
+    elif workload == ADJOINT:
+        # the reverse step's field pass: per site it reads the four FP64
+        # cotangents (32 B) and the stored FP32 fields of this step and of
+        # the step before (16 B, the latter for the next step's sums), and
+        # writes four FP64 cotangents (32 B); the first reverse step of each
+        # 50-step segment (2% of launches) has no next step's fields (72 B)
+        alg, stencil, shape = 80 * W.CFG5.sites, 7, "64 x 4 tiles, 16-plane chunks at 128^3"
+        alg_read = 48 * W.CFG5.sites
+        is_sweep = lambda k: "k_adj_fields" in k
     else:
         w = W.WORKLOADS[workload]
         esize = 4 if w.dtype == "f32" else 8
         alg, stencil, shape = 8 * esize * w.sites, w.stencil, W.BENCH_SHAPES.get(w.name, {})
+        alg_read = alg / 2
         is_sweep = lambda k: "k_sweep" in k
     copy_bytes = COPY_MIB * (1 << 20)
     is_copy = lambda k: "copy" in k.lower() and "lf::" not in k
@@ -167,7 +200,7 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
                fetch_calibration_read_only=kf_sum,
                fetch_bytes_per_launch=fetch, write_bytes_per_launch=write,
                hbm_bytes_per_launch=fetch + write, fetch_calibration=kf, write_calibration=kw,
-               fetch_over_algorithmic_reads=fetch / (alg / 2), write_over_algorithmic_writes=write / (alg / 2),
+               fetch_over_algorithmic_reads=fetch / alg_read, write_over_algorithmic_writes=write / (alg - alg_read),
                launches=len(f_sweep))
     if trace_dir:
         stats = _rows(_find(trace_dir, "kernel_stats.csv"))
@@ -199,7 +232,7 @@ def summarize(workload: str, fetch_dir: str, write_dir: str, trace_dir: str | No
                      f"{max(f_sum):.1f} KiB, a fetch factor of {kf_sum:.4f}.")
         fh.write("\n\n")
         fh.write("| quantity | per sweep launch |\n|---|---|\n")
-        fh.write(f"| algorithmic bytes (32 B/site FP32) | {alg / 1e9:.4f} GB |\n")
+        fh.write(f"| algorithmic bytes ({'80' if workload == ADJOINT else '32'} B/site) | {alg / 1e9:.4f} GB |\n")
         fh.write(f"| HBM fetch (scaled) | {fetch / 1e9:.4f} GB = {res['fetch_over_algorithmic_reads']:.3f} x algorithmic reads |\n")
         fh.write(f"| HBM write (scaled) | {write / 1e9:.4f} GB = {res['write_over_algorithmic_writes']:.3f} x algorithmic writes |\n")
         fh.write(f"| total HBM traffic | {(fetch + write) / 1e9:.4f} GB |\n")
@@ -236,7 +269,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
-    r.add_argument("--workload", default="m2phi2_512c_f32", help="a workload name, or 'ensemble'")
+    r.add_argument("--workload", default="m2phi2_512c_f32", help="a workload name, 'ensemble' or 'adjoint'")
     r.add_argument("--steps", type=int, default=4)
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="m2phi2_512c_f32")
