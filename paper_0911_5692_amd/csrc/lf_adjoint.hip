@@ -343,7 +343,8 @@ __global__ void __launch_bounds__(256) k_adj_fields(const T *__restrict__ d1, co
     // plane z in [-1, N]: one wrap suffices
     auto zoff = [&](int z) { return (int64_t)(z < 0 ? z + N : (z >= N ? z - N : z)) * NN; };
 
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    for (int base = 0; base + (int)blockIdx.x < nitems; base += gridDim.x) {
+        const int item = xcd_item(base, nitems);  // XCD-contiguous tiles share halo rows in L2
         const int tx = item % ntx, rest = item / ntx, ty = rest % nty, tz = rest / nty;
         const int x0 = tx * kAX, y0 = ty * kAY, z0 = tz * zchunk;
         const int z1 = min(z0 + zchunk, N);

@@ -61,6 +61,24 @@ struct CoefPair {
     double g1n, g2n;    // background at k+3/2 (FP64), for the reduction of f_new
 };
 
+// Hardware places block b on XCD (b mod 8).  Give each XCD a contiguous range
+// of logical tiles, so that tiles sharing halo rows run on the same L2.
+__device__ inline int xcd_remap(int b, int nb)
+{
+    constexpr int kXcd = 8;
+    const int q = nb / kXcd;
+    if (b >= q * kXcd) return b;
+    return (b % kXcd) * q + b / kXcd;
+}
+
+// The same order for a grid-stride walk over nitems items: in every round
+// where the whole grid has an item, the blocks of each XCD take a contiguous
+// range of them; the last, partial round keeps the plain order.
+__device__ inline int xcd_item(int round_base, int nitems)
+{
+    return round_base + (round_base + (int)gridDim.x <= nitems ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
+}
+
 // One realization of an ensemble, as the batched kernels see it.
 struct EnsEntry {
     void *buf[2][4];        // ping/pong deviation arrays d1, d2, e1, e2

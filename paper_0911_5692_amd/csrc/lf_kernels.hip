@@ -387,7 +387,11 @@ __global__ void __launch_bounds__(256) k_diag_march(const T *__restrict__ d1, co
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
 
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    for (int base = 0; base + (int)blockIdx.x < nitems; base += gridDim.x) {
+        // energies: XCD-contiguous tiles share their ring rows in L2 (3% faster
+        // at 512^3); rho/p, which also streams two output arrays, runs 7%
+        // faster in the plain order
+        const int item = MODE == 0 ? xcd_item(base, nitems) : base + (int)blockIdx.x;
         const int tx = item % ntx, rest = item / ntx, ty = rest % nty, tz = rest / nty;
         const int x0 = tx * kDiagX, y0 = ty * kDiagY, z0 = tz * zchunk;
         const int z1 = min(z0 + zchunk, N);

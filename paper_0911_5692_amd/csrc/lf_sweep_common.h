@@ -144,14 +144,4 @@ __device__ inline void for_each_item(int *queue, int nitems, F &&fn)
     }
 }
 
-// Hardware places block b on XCD (b mod 8).  Give each XCD a contiguous range
-// of logical tiles, so that tiles sharing halo rows run on the same L2.
-__device__ inline int xcd_remap(int b, int nb)
-{
-    constexpr int kXcd = 8;
-    const int q = nb / kXcd;
-    if (b >= q * kXcd) return b;
-    return (b % kXcd) * q + b / kXcd;
-}
-
 }  // namespace lf

@@ -6,6 +6,8 @@ on.  The GPU parity tests check the kernels themselves; these catch an
 indexing mistake on the CPU, before any launch, at sizes (ragged tiles, N
 below the tile width, grids smaller than the item list) that are cheap here.
 
+* The XCD-contiguous order in which the grid-stride kernels walk their
+  items visits every item exactly once.
 * k_diag_march (energies, rho/p): 64 x 4 tiles marching z with three LDS
   planes and a one-cell ring.  Every LDS index is in range, every gathered
   neighbour of an evaluated site is its periodic neighbour, and every site is
@@ -45,6 +47,28 @@ def ring_cell(ST, c):
     return c-DY, DY
 
 
+def xcd_remap(b, nb):
+    """Block b's logical tile when each XCD (b mod 8) takes a contiguous range."""
+    q = nb // 8
+    return b if b >= q * 8 else (b % 8) * q + b // 8
+
+
+def xcd_items(blk, items, grid):
+    """Items block blk walks (xcd_item in lf_internal.h): XCD-contiguous
+    ranges in every full round, the plain order in the last partial round."""
+    base = 0
+    while base + blk < items:
+        yield base + (xcd_remap(blk, grid) if base + grid <= items else blk)
+        base += grid
+
+
+@pytest.mark.parametrize("items,grid", [(512, 512), (1000, 512), (1024, 512), (13, 5), (64, 64), (70, 9),
+                                        (2048, 2048), (7, 7), (100, 1)])
+def test_xcd_item_order_visits_every_item_once(items, grid):
+    seen = Counter(i for b in range(grid) for i in xcd_items(b, items, grid))
+    assert sorted(seen) == list(range(items)) and set(seen.values()) == {1}
+
+
 def shape(N, rows):
     ntx = (N+DX-1)//DX; nty = (N+DY-1)//DY; tiles = ntx*nty
     nz = max(1, min(N, rows//tiles)); zc = (N+nz-1)//nz; nz = (N+zc-1)//zc
@@ -67,7 +91,7 @@ def check_diag(N, ST, rows=2048):
     # interior and ring slots never collide
     assert not set(slot) & set(rslot[hasr])
     for blk in range(grid):
-        for item in range(blk, items, grid):
+        for item in xcd_items(blk, items, grid):
             tx = item % ntx; rest = item // ntx; ty = rest % nty; tz = rest // nty
             x0, y0, z0 = tx*DX, ty*DY, tz*zc; z1 = min(z0+zc, N)
             assert z0 < N
@@ -275,7 +299,7 @@ def check_adj(N, rows=512):
     assert slot.max() < APL and rslot.min() >= 0 and rslot.max() < APL
     assert not set(slot) & set(rslot[hasr])
     for blk in range(grid):
-        for item in range(blk, items, grid):
+        for item in xcd_items(blk, items, grid):
             tx = item % ntx
             rest = item // ntx
             ty, tz = rest % nty, rest // nty
