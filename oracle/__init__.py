@@ -21,18 +21,29 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lf_oracle.c")
-LIB = os.path.join(HERE, "liblf_oracle.so")
+# LF_ORACLE_LIB selects another build of the same source (the sanitizer
+# build below); by default the plain optimised one.
+LIB = os.environ.get("LF_ORACLE_LIB") or os.path.join(HERE, "liblf_oracle.so")
+ASAN_LIB = os.path.join(HERE, "liblf_oracle_asan.so")
 CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
           "-fPIC", "-shared"]
+# AddressSanitizer and UndefinedBehaviorSanitizer, every finding fatal; the
+# library is loaded into an uninstrumented Python with the gcc runtimes
+# preloaded (see tests/test_oracle_sanitized.py)
+ASAN_CFLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (always, when force is true)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"], check=True, cwd=HERE)
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (always, when force is true); sanitize=True
+    builds the AddressSanitizer/UBSan variant instead."""
+    out = ASAN_LIB if sanitize else LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        flags = [f for f in CFLAGS if f != "-O2"] + ASAN_CFLAGS if sanitize else CFLAGS
+        subprocess.run(["gcc", *flags, "-o", tmp, SRC, "-lm"], check=True, cwd=HERE)
+        os.replace(tmp, out)
+    return out
 
 
 class _Params(ctypes.Structure):

@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "liblf.so")
 BW_CEILING = os.path.join(PKG, "bw_ceiling")
 SOURCES = ["lf_api.hip", "lf_kernels.hip", "lf_sweep.hip", "lf_sweep27.hip", "lf_slab7.hip", "lf_slab27.hip",
            "lf_adjoint.hip", "lf_fft.hip"]
-LIBS = ["-L/opt/rocm/lib", "-lhipfft"]
+LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-lrocprofiler-sdk-roctx"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

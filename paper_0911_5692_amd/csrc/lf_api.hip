@@ -3,6 +3,8 @@
 #include "lf_internal.h"
 #include "../../include/lf.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <math.h>
 #include <stdarg.h>
@@ -18,6 +20,16 @@ using namespace lf;
 namespace {
 
 thread_local std::string g_err;
+
+// A named host range for profilers (rocTX; visible under rocprofv3
+// --marker-trace) around each entry point that enqueues or waits for device
+// work.  It costs a few host instructions when no profiler is attached.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int fail(int code, const char *fmt, ...)
 {
@@ -442,6 +454,7 @@ int lf_destroy(lf_ctx *c)
 static int init_common(lf_ctx *c, const void *f1, const void *f2, const void *v1, const void *v2,
                        int in_dtype, double a0, double ad0, int physical)
 {
+    TraceRange range_("lf_init");
     if (!c) return fail(LF_EINVAL, "ctx is NULL");
     int rc;
     if ((rc = check_ptr(f1, "f1")) || (rc = check_ptr(f2, "f2")) || (rc = check_ptr(v1, "v1")) ||
@@ -488,6 +501,7 @@ int lf_init_physical(lf_ctx *c, const void *f1, const void *f2, const void *u1, 
 
 int lf_step(lf_ctx *c, int64_t n)
 {
+    TraceRange range_("lf_step");
     if (!c) return fail(LF_EINVAL, "ctx is NULL");
     if (n < 0) return fail(LF_EINVAL, "n=%lld < 0", (long long)n);
     if (!c->inited) return fail(LF_ESTATE, "lf_step before lf_init");
@@ -529,6 +543,7 @@ int lf_last_step_ms(lf_ctx *c, double *ms)
 
 int lf_energies(lf_ctx *c, lf_report *out)
 {
+    TraceRange range_("lf_energies");
     if (!c || !out) return fail(LF_EINVAL, "NULL argument");
     if (!c->inited) return fail(LF_ESTATE, "lf_energies before lf_init");
     const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
@@ -556,6 +571,7 @@ int lf_energies(lf_ctx *c, lf_report *out)
 
 int lf_rho_p(lf_ctx *c, void *rho, void *p, int out_dtype, double *avg)
 {
+    TraceRange range_("lf_rho_p");
     if (!c || !avg) return fail(LF_EINVAL, "NULL argument");
     if (!c->inited) return fail(LF_ESTATE, "lf_rho_p before lf_init");
     if (out_dtype != LF_F32 && out_dtype != LF_F64) return fail(LF_EINVAL, "out_dtype=%d", out_dtype);
@@ -771,6 +787,7 @@ static int slab_sweep_impl(lf_ctx *c, int nz, int zchunk, const void *const in[4
 int lf_slab_sweep(lf_ctx *c, int nz, int zchunk, const void *const in[4], const void *const lo[4],
                   const void *const hi[2], void *const out[4], double *partials, int64_t partial_rows)
 {
+    TraceRange range_("lf_slab_sweep");
     return slab_sweep_impl(c, nz, zchunk, in, lo, hi, out, partials, partial_rows);
 }
 
@@ -903,6 +920,7 @@ int lf_adj_workspace_bytes(const lf_params *p, int64_t n, int K, size_t *out_byt
 int lf_adj_forward(lf_ctx *c, int64_t n, int K, const double *w, void *adj_ws, size_t ws_bytes,
                    double *loss)
 {
+    TraceRange range_("lf_adj_forward");
     if (!c || !w || !loss) return fail(LF_EINVAL, "NULL argument");
     if (!c->inited || c->hstep != 0) return fail(LF_ESTATE, "lf_adj_forward needs a context just initialised");
     if (n < 1 || K < 1) return fail(LF_EINVAL, "n and K must be >= 1");
@@ -930,6 +948,7 @@ int lf_adj_forward(lf_ctx *c, int64_t n, int K, const double *w, void *adj_ws, s
 int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2, void *g_v1, void *g_v2,
                     double *dL_da0, double *dL_dad0)
 {
+    TraceRange range_("lf_adj_backward");
     if (!c || !dL_dG || !dL_da0 || !dL_dad0) return fail(LF_EINVAL, "NULL argument");
     if (!c->adj_ready) return fail(LF_ESTATE, "lf_adj_backward needs a preceding lf_adj_forward");
     void *go[4] = {g_f1, g_f2, g_v1, g_v2};
@@ -1103,6 +1122,7 @@ int lf_spectrum_workspace_bytes(const lf_params *p, size_t *out_bytes)
 
 int lf_spectrum(lf_ctx *c, int which, int nbins, double *power, double *count, void *workspace, size_t ws_bytes)
 {
+    TraceRange range_("lf_spectrum");
     if (!c) return fail(LF_EINVAL, "ctx is NULL");
     if (which < 0 || which > 3) return fail(LF_EINVAL, "which=%d: 0..3 = f1, f2, v1, v2", which);
     const int nmax = spectrum_bins(c->p.N);
@@ -1654,6 +1674,7 @@ int lf_ens_init_physical(lf_ens *e, int r, const void *f1, const void *f2, const
 
 int lf_ens_step(lf_ens *e, int64_t n)
 {
+    TraceRange range_("lf_ens_step");
     if (!e) return fail(LF_EINVAL, "ensemble is NULL");
     if (n < 0) return fail(LF_EINVAL, "n=%lld < 0", (long long)n);
     int rc = ens_check_inited(e);
