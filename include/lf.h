@@ -312,7 +312,10 @@ int lf_autotune(const lf_params *p, void *stream, void *workspace, size_t ws_byt
  * steps 0, K, 2K, ... are checkpointed in a caller-owned workspace of
  * lf_adj_workspace_bytes bytes; the backward pass recomputes each K-step
  * segment from its checkpoint, keeps its K states in the same workspace and
- * runs the reverse steps on the exact forward states.  Cotangents are FP64. */
+ * runs the reverse steps on the exact forward states.  Two segment buffers:
+ * segment s - 1 is recomputed on a second stream of the context (default
+ * priority) while the reverse steps of segment s run on its own stream.
+ * Cotangents are FP64. */
 int lf_adj_workspace_bytes(const lf_params *p, int64_t n, int K, size_t *out_bytes);
 /* Context just initialised (no step yet).  Runs n steps (the context then
  * holds step n) and returns the loss.  Blocking.  adj_ws must stay alive

@@ -204,6 +204,7 @@ struct lf_ctx {
     Shape sh;
     hipStream_t stream;
     hipStream_t cap;
+    hipStream_t aux;    // the adjoint backward's recompute stream (default priority)
     int device;         // current device at lf_create (the stream's device)
     char *ws;
     void *buf[2][4];
@@ -445,6 +446,7 @@ int lf_destroy(lf_ctx *c)
         for (int b = 0; b < 2; ++b)
             if (c->g[j][b]) (void)hipGraphExecDestroy(c->g[j][b]);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -865,8 +867,10 @@ AdjLayout adj_layout(const lf_params *p, int64_t n, int K)
     L.slot_bytes = 4 * L.arr_bytes + align_up(sizeof(DevScalars)) + align_up(8 * sizeof(double));
     size_t off = 0;
     L.ck = off; off += (size_t)L.nck * L.slot_bytes;
-    L.seg = off; off += (size_t)K * 4 * L.arr_bytes;
-    L.tape = off; off = align_up(off + (size_t)K * sizeof(DevScalars));
+    // two segment buffers and tapes: the backward pass recomputes segment
+    // s - 1 into one while the reverse steps of segment s read the other
+    L.seg = off; off += 2 * (size_t)K * 4 * L.arr_bytes;
+    L.tape = off; off = align_up(off + 2 * (size_t)K * sizeof(DevScalars));
     L.lam = off; off += 8 * align_up(n3 * sizeof(double));
     L.part = off; off = align_up(off + (size_t)kRedBlocks * kNAdjPart * sizeof(double));
     L.A = off; off = align_up(off + 8 * sizeof(double));
@@ -890,15 +894,43 @@ int save_slot(lf_ctx *c, char *slot, const AdjLayout &L)
 
 // Checkpoint `slot` back: its four arrays into `arrays` (4 x arr_bytes apart),
 // its scalars and pending sums into the context.
-int restore_slot(lf_ctx *c, const char *slot, char *arrays, const AdjLayout &L)
+int restore_slot(lf_ctx *c, const char *slot, char *arrays, const AdjLayout &L, hipStream_t st)
 {
     const size_t bytes = (size_t)c->p.N * c->p.N * c->p.N * esize(c->p.dtype);
     for (int j = 0; j < 4; ++j)
         HIPCHK(hipMemcpyAsync(arrays + j * L.arr_bytes, slot + j * L.arr_bytes, bytes, hipMemcpyDeviceToDevice,
-                              c->stream));
+                              st));
     const char *sc = slot + 4 * L.arr_bytes;
-    HIPCHK(hipMemcpyAsync(c->S, sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
-    launch_set_pending(c->part, c->sh.rows, (const double *)(sc + align_up(sizeof(DevScalars))), c->stream);
+    HIPCHK(hipMemcpyAsync(c->S, sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
+    launch_set_pending(c->part, c->sh.rows, (const double *)(sc + align_up(sizeof(DevScalars))), st);
+    HIPCHK(hipGetLastError());
+    return LF_OK;
+}
+
+// Recompute segment s into segment buffer b on stream st: buffer slot j
+// receives the state before step j (the sweep of step j - 1 writes it there
+// directly) and the tape entry j the scalars before step j; the segment's
+// last step is not needed.  Uses the context's scalars, coefficients and
+// partial rows (and nothing the reverse steps read).
+int recompute_segment(lf_ctx *c, char *ws, const AdjLayout &L, int64_t s, int b, hipStream_t st)
+{
+    const int64_t n = c->adj_n;
+    const int K = c->adj_K;
+    char *seg = ws + L.seg + (size_t)b * K * 4 * L.arr_bytes;
+    DevScalars *tape = (DevScalars *)(ws + L.tape) + (size_t)b * K;
+    int rc;
+    if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, seg, L, st))) return rc;
+    const int64_t m = (n - s * K) < K ? (n - s * K) : K;
+    for (int64_t j = 0; j < m; ++j) {
+        if (j + 1 < m) {
+            char *a = seg + (size_t)j * 4 * L.arr_bytes, *nb = a + 4 * L.arr_bytes;
+            const void *in[4] = {a, a + L.arr_bytes, a + 2 * L.arr_bytes, a + 3 * L.arr_bytes};
+            void *out[4] = {nb, nb + L.arr_bytes, nb + 2 * L.arr_bytes, nb + 3 * L.arr_bytes};
+            enqueue_step_io(c, in, out, st, nullptr, tape + j);
+        } else {
+            HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
+        }
+    }
     HIPCHK(hipGetLastError());
     return LF_OK;
 }
@@ -973,31 +1005,46 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
     const void *s4[4] = {c->buf[c->cur][0], c->buf[c->cur][1], c->buf[c->cur][2], c->buf[c->cur][3]};
     launch_adj_seed(stencil_of(&c->p), c->p.dtype, s4, c->p.N, c->P, c->S, wd, lam[0], part, kRedBlocks, A, c->stream);
     HIPCHK(hipGetLastError());
+    // The reverse steps of segment s run on the context's stream while the
+    // recompute of segment s - 1 runs on the auxiliary stream, into the other
+    // segment buffer.  Events: seg_ready[b] after a recompute into buffer b,
+    // seg_free[b] after the reverse steps that read buffer b; the first
+    // recompute waits for the seed, which reads the context's final state.
+    if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    hipEvent_t ev[5] = {};
+    for (int i = 0; i < 5 && rc == LF_OK; ++i)
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
+            rc = fail(LF_EHIP, "hipEventCreateWithFlags failed");
+    hipEvent_t seeded = ev[0], seg_ready[2] = {ev[1], ev[2]}, seg_free[2] = {ev[3], ev[4]};
+    auto check = [&](hipError_t e, const char *what) {
+        if (rc == LF_OK && e != hipSuccess) rc = fail(LF_EHIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    if (rc == LF_OK) {
+        check(hipEventRecord(seeded, c->stream), "hipEventRecord");
+        check(hipStreamWaitEvent(c->aux, seeded, 0), "hipStreamWaitEvent");
+    }
     int li = 0;
-    DevScalars *tape = (DevScalars *)(ws + L.tape);
-    for (int64_t s = L.nck - 1; s >= 0; --s) {
-        // recompute the segment: segment slot j receives the state before
-        // step j (the sweep of step j - 1 writes it there directly) and the
-        // tape the scalars before step j; the segment's last step is not
-        // needed
-        if ((rc = restore_slot(c, ws + L.ck + s * L.slot_bytes, ws + L.seg, L))) return rc;
-        const int64_t m = (n - s * K) < K ? (n - s * K) : K;
-        // (the scale-factor kernel of step j writes tape j; the segment's
-        // last state, whose step is skipped, is copied)
-        for (int64_t j = 0; j < m; ++j) {
-            if (j + 1 < m) {
-                char *a = ws + L.seg + (size_t)j * 4 * L.arr_bytes, *b = a + 4 * L.arr_bytes;
-                const void *in[4] = {a, a + L.arr_bytes, a + 2 * L.arr_bytes, a + 3 * L.arr_bytes};
-                void *out[4] = {b, b + L.arr_bytes, b + 2 * L.arr_bytes, b + 3 * L.arr_bytes};
-                enqueue_step_io(c, in, out, c->stream, nullptr, tape + j);
-            } else {
-                HIPCHK(hipMemcpyAsync(tape + j, c->S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
-            }
+    const int64_t last = L.nck - 1;
+    if (rc == LF_OK && (rc = recompute_segment(c, ws, L, last, (int)(last & 1), c->aux)) == LF_OK)
+        check(hipEventRecord(seg_ready[last & 1], c->aux), "hipEventRecord");
+    for (int64_t s = last; s >= 0 && rc == LF_OK; --s) {
+        const int b = (int)(s & 1);
+        // the next segment down goes into the other buffer once the reverse
+        // steps of segment s + 1, which read it, are done
+        if (s > 0) {
+            if (s + 1 <= last) check(hipStreamWaitEvent(c->aux, seg_free[b ^ 1], 0), "hipStreamWaitEvent");
+            if (rc == LF_OK && (rc = recompute_segment(c, ws, L, s - 1, b ^ 1, c->aux)) == LF_OK)
+                check(hipEventRecord(seg_ready[b ^ 1], c->aux), "hipEventRecord");
         }
+        check(hipStreamWaitEvent(c->stream, seg_ready[b], 0), "hipStreamWaitEvent");
+        if (rc) break;
         // reverse steps; inside a segment the fields pass of step j also
         // forms the sums of step j - 1 (its stored state is at hand)
+        const int64_t m = (n - s * K) < K ? (n - s * K) : K;
+        const char *seg = ws + L.seg + (size_t)b * K * 4 * L.arr_bytes;
+        const DevScalars *tape = (const DevScalars *)(ws + L.tape) + (size_t)b * K;
         for (int64_t j = m - 1; j >= 0; --j) {
-            const char *src = ws + L.seg + (size_t)j * 4 * L.arr_bytes;
+            const char *src = seg + (size_t)j * 4 * L.arr_bytes;
             AdjStep a{};
             a.d1 = src;
             a.d2 = src + L.arr_bytes;
@@ -1014,8 +1061,13 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
                             cf, c->stream);
             li ^= 1;
         }
-        HIPCHK(hipGetLastError());
+        check(hipGetLastError(), "reverse step launch");
+        check(hipEventRecord(seg_free[b], c->stream), "hipEventRecord");
     }
+    if (c->aux) check(hipStreamSynchronize(c->aux), "hipStreamSynchronize");
+    for (int i = 0; i < 5; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (rc) return rc;
     launch_adj_desync(c->p.N, c->p.dt, lam[li], A, c->stream);
     for (int j = 0; j < 4; ++j)
         HIPCHK(hipMemcpyAsync(go[j], lam[li][j], n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
