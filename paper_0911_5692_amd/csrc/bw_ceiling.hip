@@ -10,6 +10,12 @@
 //          (non-temporal stores), blocks in XCD-contiguous tile order;
 //   chunk  the same march with z-chunks from 1 to N planes, from
 //          short-lived blocks in address order to the sweep's long marches;
+//   halo   a chunk of planes [z0, z1) copied with the sweep's read
+//          footprint: d (arrays 0, 1) on planes z0-2 .. z1, rows y0-2 ..
+//          y0+TY and columns x0-2 .. x0+TX+1, e (arrays 2, 3) on planes
+//          z0-1 .. z1-1 with the row y0-1 and column x0-1 (what the 27-point
+//          sweep reads, a superset of the 7-point one), from registers only:
+//          what short chunks would cost a stencil sweep;
 // plus read-only and write-only kernels.  Every configuration is timed over
 // 20 launches after 5 warm-up launches; rates are the kernel's bytes (32 B
 // per site for copies, 16 B for read or write only) over its average time.
@@ -142,6 +148,93 @@ __global__ void __launch_bounds__(256) k_march(const float *__restrict__ a0, con
     }
 }
 
+// ---------------------------------------------------------------- halo footprint
+
+// Planes [z0, z1) of a TX x TY tile copied (arrays 0..3 at the tile's own
+// sites) while the reads of the sweep's halo are made too: each loaded halo
+// value feeds a sum that is stored only if it is exactly 1234.5 (never, for
+// zero data).  Periodic wrap in x, y and z keeps every read in range.
+template <int TX, int TY>
+__global__ void __launch_bounds__(256) k_halo(const float *__restrict__ d1, const float *__restrict__ d2,
+                                              const float *__restrict__ e1, const float *__restrict__ e2,
+                                              float *__restrict__ b0, float *__restrict__ b1, float *__restrict__ b2,
+                                              float *__restrict__ b3, float *__restrict__ out, int N, int zchunk,
+                                              int ntx, int nty)
+{
+    constexpr int RPR = 256 / TX, KI = TY / RPR;
+    // d halo: rows y0-2, y0-1, y0+TY (TX+4 wide from x0-2) and columns
+    // x0-2, x0-1, x0+TX, x0+TX+1 of rows y0 .. y0+TY-1; e halo: row y0-1
+    // (from x0-1 to x0+TX-1) and column x0-1 of rows y0 .. y0+TY-1
+    constexpr int NHD = 3 * (TX + 4) + 4 * TY, NHM = (NHD + 255) / 256;
+    constexpr int NHE = TX + 1 + TY, NEM = (NHE + 255) / 256;
+    static_assert(256 % TX == 0 && TY % RPR == 0, "tile shape");
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, r = tile / ntx, ty = r % nty, tz = r / nty;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int z0 = tz * zchunk, z1 = min(z0 + zchunk, N);
+    const int t = threadIdx.x, cx = t % TX, cy = t / TX;
+    const long NN = (long)N * N;
+    auto wrap = [N](int v) { return ((v % N) + N) % N; };
+    int g[KI], hd[NHM], he[NEM];
+#pragma unroll
+    for (int k = 0; k < KI; ++k) g[k] = (y0 + cy + RPR * k) * N + x0 + cx;
+#pragma unroll
+    for (int m = 0; m < NHM; ++m) {
+        int c = t + 256 * m, x, y;
+        if (c >= NHD) c = 0;  // a repeated cell: still in range
+        if (c < 3 * (TX + 4)) {
+            const int row = c / (TX + 4);
+            x = c % (TX + 4) - 2;
+            y = row == 0 ? -2 : (row == 1 ? -1 : TY);
+        } else {
+            const int cc = c - 3 * (TX + 4), col = cc / TY;
+            y = cc % TY;
+            x = col == 0 ? -2 : (col == 1 ? -1 : (col == 2 ? TX : TX + 1));
+        }
+        hd[m] = wrap(y0 + y) * N + wrap(x0 + x);
+    }
+#pragma unroll
+    for (int m = 0; m < NEM; ++m) {
+        const int c = t + 256 * m < NHE ? t + 256 * m : 0;
+        const int x = c < TX + 1 ? c - 1 : -1, y = c < TX + 1 ? -1 : c - (TX + 1);
+        he[m] = wrap(y0 + y) * N + wrap(x0 + x);
+    }
+    float acc = 0.f;
+    for (int z = z0 - 2; z <= z1; ++z) {
+        const long o = (long)wrap(z) * NN;
+        float v1[KI], v2[KI], w1[KI], w2[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            v1[k] = d1[o + g[k]];
+            v2[k] = d2[o + g[k]];
+        }
+#pragma unroll
+        for (int m = 0; m < NHM; ++m) acc += d1[o + hd[m]] + d2[o + hd[m]];
+        if (z >= z0 - 1 && z < z1) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                w1[k] = e1[o + g[k]];
+                w2[k] = e2[o + g[k]];
+            }
+#pragma unroll
+            for (int m = 0; m < NEM; ++m) acc += e1[o + he[m]] + e2[o + he[m]];
+        }
+        if (z >= z0 && z < z1) {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) {
+                __builtin_nontemporal_store(v1[k], b0 + o + g[k]);
+                __builtin_nontemporal_store(v2[k], b1 + o + g[k]);
+                __builtin_nontemporal_store(w1[k], b2 + o + g[k]);
+                __builtin_nontemporal_store(w2[k], b3 + o + g[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KI; ++k) acc += v1[k] + v2[k];
+        }
+    }
+    if (acc == 1234.5f) out[0] = acc;
+}
+
 // ---------------------------------------------------------------- driver
 
 struct Arrays {
@@ -216,6 +309,20 @@ static void march(const Arrays &A, int zchunk, const char *order)
     report(order, buf, 32.0 * A.n, ms);
 }
 
+template <int TX, int TY>
+static void halo(const Arrays &A, int zchunk)
+{
+    const int N = A.N, ntx = N / TX, nty = N / TY, nzc = (N + zchunk - 1) / zchunk;
+    const double ms = time_ms([&] {
+        hipLaunchKernelGGL((k_halo<TX, TY>), dim3(ntx * nty * nzc), dim3(256), 0, 0, A.a[0], A.a[1], A.a[2], A.a[3],
+                           A.b[0], A.b[1], A.b[2], A.b[3], A.out, N, zchunk, ntx, nty);
+    });
+    char buf[128];
+    snprintf(buf, sizeof buf, "%dx%d tiles, %d-plane chunks, %d blocks, XCD-contiguous", TX, TY, zchunk,
+             ntx * nty * nzc);
+    report("halo", buf, 32.0 * A.n, ms);
+}
+
 int main(int argc, char **argv)
 {
     Arrays A;
@@ -264,5 +371,8 @@ int main(int argc, char **argv)
     march<256, 1, false>(A, N, "march");
     for (int zc = 1; zc <= N; zc *= 2) march<256, 1, false>(A, zc, "chunk");
     for (int zc = 1; zc <= N; zc *= 4) march<128, 8, false>(A, zc, "chunk");
+    for (int zc : {1, 2, 4, 8, 16, 64, N / 2}) halo<128, 8>(A, zc);
+    for (int zc : {1, 4, 16, N / 2}) halo<256, 4>(A, zc);
+    for (int zc : {1, 4, 16}) halo<256, 8>(A, zc);
     return 0;
 }

@@ -69,6 +69,39 @@ def test_adjoint_matches_oracle_adjoint(kind, dtype, tol):
 
 
 @pytest.mark.timeout(900)
+def test_checkpoint_interval_and_repeats_on_one_context():
+    """The backward pass recomputes segment s-1 on a second stream while the
+    reverse steps of segment s run.  On one context: a single segment (no
+    overlap), segments of 7 and 3 steps (ragged last ones, odd and even
+    counts) give the same gradients up to the order of the step sums at
+    segment starts, and a repeat of the first configuration gives bitwise the
+    same result."""
+    m = _model("lphi4", 12)
+    f1, f2, v1, v2, ad0 = _state(m, 5)
+    lat = Lattice(N=m.N, L=m.L, dt=m.dt, beta=m.beta, c1=m.c1, G=m.G, r=m.r, s=m.s, kappa2=m.kappa2,
+                  dtype=torch.float32)
+    n, res = 40, []
+    for K in (40, 7, 3, 40):
+        lat.init(to_dev(f1), to_dev(f2), to_dev(v1), to_dev(v2), 1.0, ad0)
+        loss = lat.adjoint_forward(n, K, WEIGHTS)
+        g = lat.adjoint_backward(1.0)
+        res.append((K, loss, {k: (v.clone() if torch.is_tensor(v) else v) for k, v in g.items()}))
+    lat.close()
+    K0, loss0, g0 = res[0]
+    for K, loss, g in res[1:]:
+        assert loss == loss0, K
+        for k, v in g.items():
+            if torch.is_tensor(v):
+                err = float((v - g0[k]).abs().max() / g0[k].abs().max())
+                log(f"[adj] K={K} d/d{k} vs K={K0}: {err:.1e}")
+                assert err <= 1e-12, (K, k)
+            else:
+                assert abs(v - g0[k]) <= 1e-12 * abs(g0[k]), (K, k)
+    _, _, g3 = res[3]
+    for k, v in g3.items():
+        assert (torch.equal(v, g0[k]) if torch.is_tensor(v) else v == g0[k]), k
+
+
 def test_workload5_adjoint_vs_finite_differences():
     """128^3 lambda phi^4 (G = 100), FP32 lattice, 500 steps, checkpoints every
     50: dL/dG, the derivative along 8 random directions of f_phi(0) and along
