@@ -46,8 +46,12 @@
  *
  * Ownership.  The caller allocates every device buffer (inputs, outputs and
  * the workspace sized by lf_workspace_bytes) and keeps it alive until
- * lf_destroy; a context owns only host-side state and the HIP graphs it
- * captured.  A context is not thread-safe: use one context per stream.
+ * lf_destroy; a context owns only host-side state, the HIP graphs it
+ * captured and the streams and events it creates (a capture stream, the
+ * adjoint's recompute stream, timing events; default priority), all on the
+ * device that was current at lf_create (the stream's device), whatever
+ * device is current later.  A context is not thread-safe: use one context
+ * per stream.
  *
  * Errors.  Every call returns an lf_status.  No C++ exception crosses the
  * ABI.  lf_last_error() returns a thread-local message for the last failure.

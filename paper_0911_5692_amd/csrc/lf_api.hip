@@ -263,8 +263,30 @@ void enqueue_step(lf_ctx *c, int cur, hipStream_t st, hipEvent_t *ev)
     enqueue_step_io(c, in, out, st, ev);
 }
 
-int ensure_events(hipEvent_t *ev0, hipEvent_t *ev1)
+// Makes dev the current device for the scope and restores the caller's on
+// exit.  Streams and events belong to the device current when they are
+// created, so the ones a context creates after lf_create (capture streams,
+// events, the adjoint's second stream) are created inside such a scope on
+// the context's device, whatever device the caller has made current since.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess) prev = cur;
+    }
+    ~DeviceScope()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceScope(const DeviceScope &) = delete;
+    DeviceScope &operator=(const DeviceScope &) = delete;
+};
+
+int ensure_events(int dev, hipEvent_t *ev0, hipEvent_t *ev1)
 {
+    if (*ev0 && *ev1) return LF_OK;
+    DeviceScope scope(dev);
     if (!*ev0) HIPCHK(hipEventCreate(ev0));
     if (!*ev1) HIPCHK(hipEventCreate(ev1));
     return LF_OK;
@@ -272,6 +294,7 @@ int ensure_events(hipEvent_t *ev0, hipEvent_t *ev1)
 
 int capture(lf_ctx *c, int nsteps, int start, hipGraphExec_t *exec)
 {
+    DeviceScope scope(c->device);
     if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int cur = start;
@@ -517,7 +540,7 @@ int lf_step(lf_ctx *c, int64_t n)
             if ((rc = ensure_graph(c, j, p))) return rc;
             if (j == 0) p ^= 1;
         }
-    if ((rc = ensure_events(&c->ev0, &c->ev1))) return rc;
+    if ((rc = ensure_events(c->device, &c->ev0, &c->ev1))) return rc;
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     for (; n >= K; n -= K) HIPCHK(hipGraphLaunch(c->g[c->logK][c->cur], c->stream));
     for (int j = c->logK - 1; j >= 0; --j)
@@ -822,6 +845,7 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
     if (!c || !ms) return fail(LF_EINVAL, "NULL argument");
     if (n < 1 || n_out < 1) return fail(LF_EINVAL, "n and n_out must be >= 1");
     if (!c->inited) return fail(LF_ESTATE, "lf_time_kernels before lf_init");
+    DeviceScope scope(c->device);
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     double acc[3] = {0.0, 0.0, 0.0};
@@ -1010,6 +1034,7 @@ int lf_adj_backward(lf_ctx *c, double dL, double *dL_dG, void *g_f1, void *g_f2,
     // segment buffer.  Events: seg_ready[b] after a recompute into buffer b,
     // seg_free[b] after the reverse steps that read buffer b; the first
     // recompute waits for the seed, which reads the context's final state.
+    DeviceScope scope(c->device);
     if (!c->aux) HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     hipEvent_t ev[5] = {};
     for (int i = 0; i < 5 && rc == LF_OK; ++i)
@@ -1381,6 +1406,7 @@ struct lf_ens {
     int R;
     int dtype, beta, stencil, tile_x, tile_y;
     hipStream_t stream, cap;
+    int device;          // current device at lf_ens_create (the stream's device)
     lf_ctx **sub;        // one context per realization, on slices of the workspace
     EnsEntry *tab;       // device table (workspace)
     int4 *items;         // device work list (workspace)
@@ -1529,6 +1555,10 @@ int lf_ens_create(int R, const lf_params *per, void *stream, void *workspace, si
     e->tile_x = ens_tile_x(&per[0]);
     e->tile_y = ens_tile_y(&per[0]);
     e->stream = (hipStream_t)stream;
+    if (hipGetDevice(&e->device) != hipSuccess) {
+        delete e;
+        return fail(LF_EHIP, "hipGetDevice failed");
+    }
     e->sub = new (std::nothrow) lf_ctx *[R]();
     size_t *so = new size_t[R + 1];
     int nitems = 0;
@@ -1657,6 +1687,7 @@ void ens_enqueue_step(lf_ens *e, int parity, hipStream_t st)
 
 int ens_capture(lf_ens *e, int nsteps, int start, hipGraphExec_t *exec)
 {
+    DeviceScope scope(e->device);
     if (!e->cap) HIPCHK(hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
     int par = start;
@@ -1733,7 +1764,7 @@ int lf_ens_step(lf_ens *e, int64_t n)
     if (rc) return rc;
     if (n == 0) return LF_OK;
     if (n >= 2 && !e->g2 && (rc = ens_capture(e, 2, 0, &e->g2))) return rc;
-    if ((rc = ensure_events(&e->ev0, &e->ev1))) return rc;
+    if ((rc = ensure_events(e->device, &e->ev0, &e->ev1))) return rc;
     HIPCHK(hipEventRecord(e->ev0, e->stream));
     while (n > 0) {
         if (n >= 2 && e->cur == 0) {

@@ -8,8 +8,8 @@ below the tile width, grids smaller than the item list) that are cheap here.
 
 * The XCD-contiguous order in which the grid-stride kernels walk their
   items visits every item exactly once.
-* k_diag_march (energies, rho/p): 64 x 4 tiles marching z with three LDS
-  planes and a one-cell ring.  Every LDS index is in range, every gathered
+* k_diag_march (energies, rho/p): 64 x 4 KI tiles (KI sites per thread)
+  marching z with three LDS planes and a one-cell ring.  Every LDS index is in range, every gathered
   neighbour of an evaluated site is its periodic neighbour, and every site is
   evaluated exactly once.
 * sweep_tile27 (27-point sweep): the staged plane covers the tile, its ring
@@ -24,20 +24,21 @@ import numpy as np
 import pytest
 
 
-# ---- k_diag_march: tile 64 x 4, LDS planes of (64 + 2) x (4 + 2) doubles
-DX, DY = 64, 4
-LW, LH = DX + 2, DY + 2
-PL = LW * LH
+# ---- k_diag_march: tile 64 x 4 KI (KI sites per thread, rows ly, ly+4, ...),
+# LDS planes of (64 + 2) x (4 KI + 2) doubles
+DX = 64
+LW = DX + 2
+DIAG_KI = {7: 2, 27: 1}  # diag_ki<ST>() in lf_kernels.hip
 BONDS = {7: [(1,0,0),(0,1,0),(0,0,1)],
          27: [(1,0,0),(0,1,0),(0,0,1),(-1,1,0),(1,1,0),(0,-1,1),(0,1,1),(-1,0,1),(1,0,1),
               (-1,-1,1),(1,-1,1),(-1,1,1),(1,1,1)]}
 
 
-def ring(ST):
+def ring(ST, DY):
     return 2*LW + 2*DY if ST == 27 else DX + DY
 
 
-def ring_cell(ST, c):
+def ring_cell(ST, c, DY):
     if ST == 27:
         if c < LW: return c-1, -1
         if c < 2*LW: return c-LW-1, DY
@@ -69,22 +70,29 @@ def test_xcd_item_order_visits_every_item_once(items, grid):
     assert sorted(seen) == list(range(items)) and set(seen.values()) == {1}
 
 
-def shape(N, rows):
+def shape(N, rows, DY):
     ntx = (N+DX-1)//DX; nty = (N+DY-1)//DY; tiles = ntx*nty
     nz = max(1, min(N, rows//tiles)); zc = (N+nz-1)//nz; nz = (N+zc-1)//zc
     items = tiles*nz
     return ntx, nty, zc, items, min(items, rows)
 
 
-def check_diag(N, ST, rows=2048):
+def check_diag(N, ST, rows=2048, KI=None):
+    KI = KI or DIAG_KI[ST]
+    DY = 4 * KI
+    PL = LW * (DY + 2)
     rng = np.random.default_rng(N*100+ST)
     f = rng.standard_normal((N, N, N))   # [z, y, x]
-    ntx, nty, zc, items, grid = shape(N, rows)
+    ntx, nty, zc, items, grid = shape(N, rows, DY)
     seen = np.zeros((N, N, N), int)
-    t = np.arange(256); lx = t & 63; ly = t >> 6
+    # a thread's KI sites as KI x 256 lanes
+    t = np.tile(np.arange(256), KI); lx = t & 63; ly = (t >> 6) + 4 * np.repeat(np.arange(KI), 256)
     slot = (ly+1)*LW + lx + 1
-    NR = ring(ST); hasr = t < NR
-    rc = [ring_cell(ST, int(c)) if c < NR else (0, 0) for c in t]
+    assert len(set(slot)) == len(slot)
+    t = np.arange(256)
+    NR = ring(ST, DY); hasr = t < NR
+    assert NR <= 256
+    rc = [ring_cell(ST, int(c), DY) if c < NR else (0, 0) for c in t]
     rx = np.array([a for a, b in rc]); ry = np.array([b for a, b in rc])
     rslot = (ry+1)*LW + rx + 1
     assert slot.min() >= 0 and slot.max() < PL and rslot.min() >= 0 and rslot.max() < PL
@@ -229,20 +237,18 @@ def check_sweep27(N, TX, TY, ZC):
     return len(cnt)
 
 
+@pytest.mark.parametrize("KI", [1, 2, 4])
 @pytest.mark.parametrize("N", [4, 5, 9, 33, 67])
 @pytest.mark.parametrize("ST", [7, 27])
+def test_diag_march_indexing(N, ST, KI):
+    check_diag(N, ST, KI=KI)
 
 
-def test_diag_march_indexing(N, ST):
-    check_diag(N, ST)
-
-
+@pytest.mark.parametrize("KI", [1, 2, 4])
 @pytest.mark.parametrize("N,rows", [(17, 5), (40, 3), (9, 1)])
-
-
-def test_diag_march_items_beyond_grid(N, rows):
-    check_diag(N, 7, rows)
-    check_diag(N, 27, rows)
+def test_diag_march_items_beyond_grid(N, rows, KI):
+    check_diag(N, 7, rows, KI=KI)
+    check_diag(N, 27, rows, KI=KI)
 
 
 @pytest.mark.parametrize("case", [(4, 64, 8, 4), (5, 64, 4, 3), (7, 64, 16, 8), (12, 64, 8, 5),
