@@ -139,7 +139,8 @@ def copy_reference(N: int, reps: int = 20) -> dict:
     e.synchronize()
     ms = s.elapsed_time(e) / reps
     del src, dst
-    return {"kernel": "lf_stream_copy (16-byte loads, non-temporal 16-byte stores)", "bytes": 32 * N ** 3,
+    return {"kernel": "lf_stream_copy (one float per lane, blocks in address order, non-temporal stores)",
+            "bytes": 32 * N ** 3,
             "ms": round(ms, 5), "GBps": round(32 * N ** 3 / (ms * 1e-3) / 1e9, 1)}
 
 

@@ -219,8 +219,9 @@ int lf_last_step_ms(lf_ctx *ctx, double *ms);
 /* ---- bandwidth reference ------------------------------------------------ */
 
 /* Copy four FP32 arrays of n elements into four others (b_j = a_j): the byte
- * mix of the FP32 sweep (16 B read and 16 B written per element index) with
- * 16-byte loads and non-temporal 16-byte stores over a grid-stride loop.  It
+ * mix of the FP32 sweep (16 B read and 16 B written per element index), one
+ * element per lane over a grid that covers the arrays once in address order,
+ * with non-temporal stores (the fastest order measured for this mix).  It
  * does no arithmetic, so its rate is what the device streams for this mix;
  * the benchmark reports the sweep's bandwidth as a fraction of it.
  * Pointers: device arrays, 256-byte aligned, caller-owned, not overlapping;

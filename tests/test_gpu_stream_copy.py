@@ -1,5 +1,6 @@
 """lf_stream_copy, the benchmark's bandwidth reference: an exact copy of four
-arrays, for sizes that leave a ragged grid-stride tail."""
+arrays, for sizes that leave a partly filled last block (one element per
+lane, a grid that covers the arrays once)."""
 import pytest
 import torch
 
