@@ -88,6 +88,20 @@ def cpu_baseline(w, ic) -> dict:
         out["single_thread"] = {"value": w.sites / el1 / 1e9, "sample": "1 leapfrog step, 1 thread"}
     except OSError:
         out["single_thread"] = None
+    # 20 steps of the 256^3 workload (lambda phi^4, its own inputs), all threads
+    try:
+        from paper_0911_5692_amd import workloads as W
+        w2 = W.CFG2
+        ic2 = W.make_inputs(w2)
+        m2 = O.Model(**w2.model())
+        st2 = O.start_physical(m2, ic2["f1"], ic2["f2"], ic2["u1"], ic2["u2"], ic2["a0"])
+        t0 = time.perf_counter()
+        O.evolve(st2, 20)
+        el2 = time.perf_counter() - t0
+        out["at_256"] = {"value": w2.sites * 20 / el2 / 1e9, "sample": f"20 leapfrog steps of the {w2.N}^3 "
+                         f"workload ({w2.name}), OpenMP {cores} threads"}
+    except MemoryError:
+        out["at_256"] = None
     return out
 
 
@@ -248,17 +262,22 @@ def time_additions() -> dict:
     w5 = W.CFG5
     ic = W.make_inputs(w5)
     lat = Lattice(**w5.model(), dtype=torch.float32, device="cuda:0")
-    lat.init_physical(*(torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")), ic["a0"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.adjoint_forward(w5.steps, 50)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lat.adjoint_backward(1.0)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    out["adjoint"] = {"N": w5.N, "steps": w5.steps, "K": 50, "forward_ms": round((t1 - t0) * 1e3, 1),
-                      "backward_ms": round((t2 - t1) * 1e3, 1)}
+    dev_ic = [torch.from_numpy(ic[k]).to("cuda:0") for k in ("f1", "f2", "u1", "u2")]
+    passes = []
+    for _ in range(2):  # the second pass is reported; the first includes one-time set-up
+        lat.init_physical(*dev_ic, ic["a0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.adjoint_forward(w5.steps, 50)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.adjoint_backward(1.0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        passes.append((round((t1 - t0) * 1e3, 1), round((t2 - t1) * 1e3, 1)))
+    out["adjoint"] = {"N": w5.N, "steps": w5.steps, "K": 50, "forward_ms": passes[1][0],
+                      "backward_ms": passes[1][1], "first_forward_ms": passes[0][0],
+                      "first_backward_ms": passes[0][1]}
     lat.close()
     return out
 
