@@ -846,10 +846,11 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
     if (n < 1 || n_out < 1) return fail(LF_EINVAL, "n and n_out must be >= 1");
     if (!c->inited) return fail(LF_ESTATE, "lf_time_kernels before lf_init");
     DeviceScope scope(c->device);
-    hipEvent_t ev[4];
-    for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
-    double acc[3] = {0.0, 0.0, 0.0};
+    hipEvent_t ev[4] = {};
     int rc = LF_OK;
+    for (int i = 0; i < 4 && rc == LF_OK; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) rc = fail(LF_EHIP, "hipEventCreate failed");
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t k = 0; k < n && rc == LF_OK; ++k) {
         enqueue_step(c, c->cur, c->stream, ev);
         hipError_t e = hipGetLastError();
@@ -863,7 +864,8 @@ int lf_time_kernels(lf_ctx *c, int64_t n, double *ms, int n_out)
         c->cur ^= 1;
         c->hstep += 1;
     }
-    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 4; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (rc) return rc;
     for (int j = 0; j < n_out; ++j) ms[j] = (j < 3) ? acc[j] / (double)n : 0.0;
     return LF_OK;
