@@ -340,14 +340,16 @@ int lf_adj_backward(lf_ctx *ctx, double dL, double *dL_dG, void *g_f1, void *g_f
  * Every step is two launches for the whole ensemble, captured in a HIP
  * graph: a batched FP64 scale-factor update (one block per realization, each
  * with its own a(t), background and averages) and one persistent sweep whose
- * blocks take (realization, tile, z-chunk) work items from a device-wide
- * counter, longest item first.  The sweep tile is per_real[0].tile_x/tile_y
+ * blocks take (realization, tile, z-chunk) work items from device-wide
+ * counters: the items are split into one segment per XCD (whole z-chunks,
+ * longest first), a block takes items of its own XCD's segment and then
+ * those of the others.  The sweep tile is per_real[0].tile_x/tile_y
  * (default 64 x 8; 32-wide tiles for the 7-point stencil only) for all
  * realizations; z-chunks may differ per realization (default: the whole
  * lattice when the realizations' tile columns fill between half and all of
  * the resident grid, else N/2 planes, at least 8, or N when N < 8);
- * lf_ens_autotune picks both by measurement.  Each realization's state matches a single-lattice run
- * with the same parameters to rounding. */
+ * lf_ens_autotune picks both by measurement.  Each realization's state
+ * matches a single-lattice run with the same parameters to rounding. */
 int lf_ens_workspace_bytes(int R, const lf_params *per_real, size_t *out_bytes);
 int lf_ens_create(int R, const lf_params *per_real, void *stream, void *workspace, size_t ws_bytes,
                   lf_ens **out);
