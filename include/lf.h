@@ -158,7 +158,9 @@ int lf_workspace_bytes(const lf_params *p, size_t *out_bytes);
 int lf_create(const lf_params *p, void *stream, void *workspace, size_t ws_bytes,
               lf_ctx **out);
 
-/* Destroy a context; frees host state and graphs only.  NULL is a no-op. */
+/* Destroy a context: frees its host state, graphs, and the streams and events
+ * it created (not the caller's stream or any device buffer).  NULL is a
+ * no-op. */
 int lf_destroy(lf_ctx *ctx);
 
 /* Initialise from a synchronised program-unit state at tau = 0
