@@ -62,6 +62,7 @@ STORED = [
     # workload, stored oracle result (tests/golden/make_*_crop.py), launch shape
     (W.CFG3, "cfg3_512_crop.npz"),
     (W.PAPER_256_S27, "paper256_s27_crop.npz"),
+    (W.CFG3_S27, "cfg3s27_512_crop.npz"),
 ]
 
 
@@ -69,9 +70,11 @@ STORED = [
 @pytest.mark.parametrize("w,fixture", STORED, ids=[w.name for w, _ in STORED])
 def test_own_inputs_vs_stored_oracle(w, fixture):
     """The benchmark's 512^3 workload (7-point, 2000 steps, 128 x 8 tiles with
-    two 256-plane z-chunks) and the paper's timed 256^3 configuration
-    (27-point, 600 steps, 128 x 8 tiles with 32-plane z-chunks), each from
-    its own seeded vacuum inputs, against the stored FP64 oracle result."""
+    two 256-plane z-chunks), the paper's timed 256^3 configuration (27-point,
+    600 steps, 128 x 8 tiles with 32-plane z-chunks) and the 512^3 workload
+    with the 27-point Laplacian (240 steps in the benchmark's launch shape),
+    each from its own seeded vacuum inputs, against the stored FP64 oracle
+    result."""
     path = os.path.join(HERE, "golden", fixture)
     if not os.path.exists(path):
         pytest.fail(f"missing {path}: run the tests/golden/make_*_crop.py script that writes it")
